@@ -1,0 +1,200 @@
+"""Throughput of one Vegas iteration on one MI355X.
+
+Workload (the d = 8 Gaussian case): f(x) = prod_i exp(-(x_i - 1/2)^2/a^2)/(a sqrt(pi)),
+a = 0.1, on [0,1]^8, 50 bins per dimension, alpha = 1.5, Philox seed 0,
+1e7 events per iteration.  One step = one adaptation iteration of the whole hot
+path: points -> map -> integrand -> sums and histograms -> merge ->
+statistics -> refinement, all on the device.  The headline value is events/s
+of the FP32-mixed path; the FP64 path is timed the same way beside it.
+
+Also reported: the event kernel's roofline (VALU issue bound), the whole
+5 adaptation + 5 accumulation schedule for both precisions, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/s per Vegas iteration (d=8 Gaussian, 1e7 evts), FP32-mixed vs FP64"
+D, NBINS, A, ALPHA, EVENTS = 8, 50, 0.1, 1.5, 10_000_000
+
+# Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
+# counted in full-rate lane-slots per second.
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def alg_slots_per_event(d: int) -> int:
+    """Algorithmic VALU lane-slots per event of the mixed-precision event
+    kernel (fixed table; wide 32x32->64 multiplies and transcendentals count
+    4 slots, everything else 1):
+      Philox4x32-10: ceil(d/4) calls x 10 rounds x (2 wide mul + 2 three-way xor) = 100 ceil(d/4)
+      binning, exact: 5 per dimension
+      map: convert + fma + LDS address = 3 per dimension
+      integrand: subtract + fma per dimension, + 3 + exp (4)
+      Jacobian: 1 per dimension; sums: 10; histogram address: 1 per dimension
+    """
+    return 100 * math.ceil(d / 4) + 12 * d + 17
+
+
+def _events_per_s(ms_per_step: float) -> float:
+    return EVENTS / (ms_per_step * 1e-3)
+
+
+def time_path(precision: str, steps: int, warmup: int):
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    params = [A] + [0.5] * D
+    v = Vegas(D, NBINS, "gauss", params, precision, seed=0, alpha=ALPHA)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        v.iterate(EVENTS, refine=True, combine=False)
+    torch.cuda.synchronize()
+    v.timing_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        v.iterate(EVENTS, refine=True, combine=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+    sample_ms, merge_ms, n = v.timing_read()
+    v.timing_enable(False)
+    return {
+        "ms_per_step": total_ms / steps,
+        "wall_ms_per_step": wall * 1e3 / steps,
+        "events_per_s": _events_per_s(total_ms / steps),
+        "event_kernel_ms": sample_ms / n,
+        "merge_kernel_ms": merge_ms / n,
+    }
+
+
+def c2_schedule(precision: str):
+    """5 adaptation iterations (refined after, left out of the result), then
+    5 accumulation iterations on the frozen grid, 1e7 events each."""
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        v.iterate(EVENTS, refine=True, combine=False)
+    for _ in range(5):
+        v.iterate(EVENTS)
+    r = v.result()
+    wall = time.perf_counter() - t0
+    return {"integral": r["integral"], "sigma": r["sigma"], "chi2_dof": r["chi2_dof"],
+            "rel_err": r["sigma"] / r["integral"], "wall_ms": wall * 1e3}
+
+
+def cpu_baseline(iters: int):
+    """The FP64 oracle (single-threaded C, as it stands) on the same workload:
+    `iters` iterations of 1e7 events with refinement, seed 0."""
+    import oracle
+    pr = oracle.Problem(D, NBINS, oracle.GAUSS, [A] + [0.5] * D, seed=0, alpha=ALPHA)
+    E = oracle.uniform_edges(D, NBINS)
+    n_events = EVENTS
+    t0 = time.perf_counter()
+    for t in range(iters):
+        S1, S2, H = oracle.accumulate(pr, E, t, n_events)
+        E = oracle.refine(H, E, ALPHA)
+    dt = time.perf_counter() - t0
+    return {"value": iters * n_events / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations x {n_events:.0e} events of the d=8 workload "
+                      f"(accumulate + refine), FP64, single thread, {dt:.1f} s"}
+
+
+def copy_probe():
+    """A plain device copy of known size (256 MiB), used to scale the HBM
+    counters of a profiled run."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path is "
+              "single-device by design", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+
+    mixed = time_path("fp32_mixed", args.steps, args.warmup)
+    fp64 = None if args.mixed_only else time_path("fp64", args.steps, args.warmup)
+    sched = {} if args.mixed_only else {p: c2_schedule(p) for p in ("fp32_mixed", "fp64")}
+
+    slots = alg_slots_per_event(D)
+    t_k = mixed["event_kernel_ms"] * 1e-3
+    achieved = slots * EVENTS / t_k / 1e12
+    peak = PEAK_SLOTS / 1e12
+    out = {
+        "metric": METRIC,
+        "value": mixed["events_per_s"],
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "vegas_gauss_d8_1e7", "dim": D, "n_bins": NBINS, "a": A, "alpha": ALPHA,
+                   "events_per_iteration": EVENTS, "seed": 0, "precision": "fp32_mixed (f64 sums)",
+                   "step": "one adaptation iteration: sample+map+integrand+sums+histograms+merge+stats+refine"},
+        "roofline": {"bound": "alu", "kernel": "k_sample (event kernel)", "achieved": achieved,
+                     "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": None,
+                     "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
+        "merge_kernel_ms": mixed["merge_kernel_ms"],
+        "wall_ms_per_step": mixed["wall_ms_per_step"],
+    }
+    if fp64 is not None:
+        out["fp64"] = {"value": fp64["events_per_s"], "ms_per_step": fp64["ms_per_step"],
+                       "event_kernel_ms": fp64["event_kernel_ms"], "merge_kernel_ms": fp64["merge_kernel_ms"]}
+        out["mixed_over_fp64"] = mixed["events_per_s"] / fp64["events_per_s"]
+    if sched:
+        m, f = sched["fp32_mixed"], sched["fp64"]
+        out["c2_schedule"] = {"fp32_mixed": m, "fp64": f,
+                              "mixed_minus_fp64_in_sigma": (m["integral"] - f["integral"]) / f["sigma"],
+                              "exact": 0.99999999998770032}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+        out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

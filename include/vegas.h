@@ -1,0 +1,232 @@
+/*
+ * vegas.h -- C ABI of the MI355X (gfx950) Vegas iteration library (libvegas).
+ *
+ * The library runs the data-parallel hot path of Vegas adaptive Monte Carlo
+ * integration, the method the paper integrates with (sec. 2.2: importance
+ * sampling as implemented in Vegas -- a per-event stage that generates and
+ * weights random points, then, once an integration pass is finished, a
+ * refinement of how the random numbers are generated), on one GPU:
+ *
+ *   counter-based points -> per-dimension piecewise-linear grid map and
+ *   Jacobian -> integrand -> sums of f*w and (f*w)^2 and per-dimension,
+ *   per-bin histograms of (f*w)^2 -> iteration estimate and variance ->
+ *   grid refinement -> inverse-variance combination ("value +- error",
+ *   Table 1).
+ *
+ * Conventions for every entry point:
+ *  - All calls return a vegas_status; they never throw or abort.  On a
+ *    non-OK status vegas_last_error() returns a message (thread-local).
+ *  - Argument validation happens before any HIP call.
+ *  - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *    Every call only enqueues work on the given stream, except those marked
+ *    "synchronises", which wait for the stream to finish.
+ *  - Device memory is owned by the caller: the context lives in one
+ *    caller-allocated device workspace (see vegas_workspace_size).  The
+ *    library itself never allocates device memory; it owns only a small host
+ *    context, a small pinned host staging buffer and, for batches, a HIP graph.
+ *  - One context must not be used from two host threads at once.
+ *
+ * Limits: 1 <= dim <= 64, 2 <= n_bins <= 255, and the per-block LDS image of
+ * the grid and histograms must fit the device (dim * n_bins * 24 bytes for
+ * FP64, dim * n_bins * 16 bytes for FP32-mixed, at most 160 KiB).
+ */
+#ifndef VEGAS_H
+#define VEGAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vegas_ctx vegas_ctx;
+typedef struct vegas_batch vegas_batch;
+typedef void* vegas_stream_t; /* a hipStream_t */
+
+typedef enum {
+    VEGAS_OK = 0,
+    VEGAS_EINVAL = -1,      /* invalid argument */
+    VEGAS_ESTATE = -2,      /* call not valid in the context's current state */
+    VEGAS_EWORKSPACE = -3,  /* workspace too small or misaligned */
+    VEGAS_EHIP = -4,        /* a HIP runtime call failed (message kept) */
+    VEGAS_ENONFINITE = -5,  /* a recorded iteration had a non-finite estimate */
+    VEGAS_EUNSUPPORTED = -6 /* valid request this build does not support */
+} vegas_status;
+
+/* Integrands (sec. 3.1).  params layout (FP64, host pointer at init):
+ *  VEGAS_GAUSS     f = nu exp(-sum_i (x_i - mu_i)^2 / a^2),  nu = (a sqrt(pi))^-d
+ *                  (Eq. lepage with centre mu; mu_i = 1/2 is the paper's case)
+ *                  params = a, mu[0..d-1]                              (1 + d)
+ *  VEGAS_BIMODAL   f = nu/2 [G(x; muA) + G(x; muB)], G as above
+ *                  params = a, muA[0..d-1], muB[0..d-1]                (1 + 2d)
+ *  VEGAS_GENZ_DISC f = 0 if any x_i <= a_i, else nu exp(sum c_i x_i)  (Eq. genzdisc)
+ *                  params = c[0..d-1], a[0..d-1]                       (2d)
+ *  VEGAS_GENZ_PEAK f = nu prod 1/(c_i^-2 + (x_i - a_i)^2)              (Eq. productpeak)
+ *                  params = c[0..d-1], a[0..d-1]                       (2d)
+ * For the Genz forms nu makes the integral over [0,1]^d one (sec. 3.1). */
+enum { VEGAS_GAUSS = 0, VEGAS_BIMODAL = 1, VEGAS_GENZ_DISC = 2, VEGAS_GENZ_PEAK = 3 };
+
+/* Precision of the map and integrand.  Sums, histograms, statistics and the
+ * grid are FP64 in both. */
+enum { VEGAS_FP64 = 0, VEGAS_FP32_MIXED = 1 };
+
+/* Flags of vegas_iterate. */
+#define VEGAS_CHUNK_BEGIN 1u /* first chunk of an iteration: accumulators restart */
+#define VEGAS_CHUNK_END 2u   /* last chunk: statistics are computed, iteration recorded */
+#define VEGAS_ITER_FULL 3u   /* a whole iteration in one call */
+#define VEGAS_NO_COMBINE 4u  /* (with CHUNK_END) record it but keep it out of the combination */
+#define VEGAS_REFINE 8u      /* (with CHUNK_END) refine the grid from this iteration's histograms */
+
+typedef struct {
+    int32_t dim;          /* d */
+    int32_t n_bins;       /* N, bins per dimension */
+    int32_t integrand;    /* VEGAS_GAUSS ... */
+    int32_t precision;    /* VEGAS_FP64 or VEGAS_FP32_MIXED */
+    uint64_t seed;        /* Philox key */
+    double alpha;         /* damping exponent of the refinement (>= 0) */
+    const double* params; /* host pointer to n_params values, copied at init */
+    int32_t n_params;
+    int32_t problem;      /* problem index p in the Philox counter, 0 <= p < 2^24 */
+} vegas_desc;
+
+typedef struct {
+    double integral;      /* inverse-variance combination of the combined iterations */
+    double sigma;         /* its error */
+    double chi2_dof;      /* chi^2 per degree of freedom (NaN with one iteration) */
+    double last_integral; /* estimate of the last recorded iteration */
+    double last_sigma;    /* its error */
+    int64_t n_iter;       /* iterations recorded */
+    int64_t n_combined;   /* iterations in the combination */
+    int64_t n_events;     /* events over all recorded iterations */
+    int64_t n_nonfinite;  /* recorded iterations whose estimate or variance was not finite */
+} vegas_result_t;
+
+/* Bytes of device workspace a context for *desc needs (no HIP call). */
+vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes);
+
+/* Create a context on the current HIP device in the caller's workspace
+ * dev_ws (>= vegas_workspace_size bytes, 256-byte aligned; must stay valid
+ * until vegas_destroy) and start from the uniform grid E_k = k/N in every
+ * dimension.  The iteration index t starts at 0. */
+vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws,
+                             size_t ws_bytes, vegas_stream_t stream);
+
+/* Run n_events events (1 <= n_events <= 2^40) of the current iteration t.
+ * Event e draws, for each group j of four dimensions,
+ * Philox4x32-10(counter = (e mod 2^32, e div 2^32, t, p*256 + j),
+ * key = (seed mod 2^32, seed div 2^32)); dimension i takes word i mod 4 of
+ * group i div 4 as y = (k + 1/2)/2^32.  Within one iteration, successive
+ * chunks continue the event index (the first chunk starts at e = 0).
+ * flags: VEGAS_ITER_FULL for a one-call iteration, or CHUNK_BEGIN, none, ...,
+ * CHUNK_END over several calls; REFINE and NO_COMBINE act at CHUNK_END.
+ * At CHUNK_END: I_t = S1/M, var_t = (S2/M - I_t^2)/(M-1) over the M events
+ * of the iteration (M >= 2), the iteration is recorded and t advances. */
+vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,
+                           vegas_stream_t stream);
+
+/* Refine the grid from the histograms of the last completed iteration
+ * (ESTATE if there is none, or if they were already used for a refinement). */
+vegas_status vegas_refine(vegas_ctx* ctx, vegas_stream_t stream);
+
+/* Copy the combined result to *host_out.  Synchronises.  Returns
+ * VEGAS_ENONFINITE (with *host_out filled) if any recorded iteration was not
+ * finite. */
+vegas_status vegas_result(vegas_ctx* ctx, vegas_result_t* host_out, vegas_stream_t stream);
+
+/* Forget recorded iterations and the combination (the grid and t stay). */
+vegas_status vegas_reset_results(vegas_ctx* ctx, vegas_stream_t stream);
+
+/* Replace the integrand parameters from device memory (n_params values, FP64
+ * if is_fp32 == 0, else FP32; same layout as vegas_desc.params). */
+vegas_status vegas_set_params_device(vegas_ctx* ctx, const void* dev_params, int32_t n_params,
+                                     int32_t is_fp32, vegas_stream_t stream);
+
+/* Write (I_t, sigma_t) of the last recorded iteration to dev_out[2] (device). */
+vegas_status vegas_last_iteration_device(vegas_ctx* ctx, double* dev_out, vegas_stream_t stream);
+
+/* Adjoint of the estimate of iteration `iteration` over events [0, n_events)
+ * at fixed samples and the current (frozen) grid, Gaussian integrand only:
+ * dev_grad[j] = gout * (1/M) sum_e w_e df/dtheta_j(x_e), theta = (mu[0..d-1], a),
+ * with gout = *dev_gout (device FP64 scalar).  dev_grad is device FP64[d+1]. */
+vegas_status vegas_adjoint(vegas_ctx* ctx, int64_t iteration, int64_t n_events,
+                           const double* dev_gout, double* dev_grad, vegas_stream_t stream);
+
+/* Per-event record of events [first, first+count) of iteration `iteration`
+ * on the current grid, into device FP64 dev_out[count][3d+2]:
+ * b[0..d-1], delta[0..d-1], x[0..d-1], w, f  (values as the kernel computes
+ * them in its precision, widened to FP64).  For parity checks. */
+vegas_status vegas_dump_events(vegas_ctx* ctx, int64_t iteration, int64_t first, int64_t count,
+                               double* dev_out, vegas_stream_t stream);
+
+/* Copy grid edges (host FP64 [d][N+1]) out of / into the context.
+ * vegas_get_edges synchronises; vegas_set_edges rebuilds the kernel tables. */
+vegas_status vegas_get_edges(vegas_ctx* ctx, double* host_edges, vegas_stream_t stream);
+vegas_status vegas_set_edges(vegas_ctx* ctx, const double* host_edges, vegas_stream_t stream);
+
+/* Sums (S1, S2) and histograms H[d][N] of the last completed iteration
+ * (host FP64; either pointer may be NULL).  Synchronises. */
+vegas_status vegas_get_iteration(vegas_ctx* ctx, double* host_sums, double* host_hist,
+                                 vegas_stream_t stream);
+
+/* Checkpoint: the state is the grid, the iteration index, the recorded
+ * iterations and the combination.  Because points are counter-based, a run
+ * resumed from a state continues with the same points as an uninterrupted one.
+ * vegas_get_state synchronises. */
+vegas_status vegas_state_size(const vegas_ctx* ctx, size_t* bytes);
+vegas_status vegas_get_state(vegas_ctx* ctx, void* host_buf, size_t bytes, vegas_stream_t stream);
+vegas_status vegas_set_state(vegas_ctx* ctx, const void* host_buf, size_t bytes,
+                             vegas_stream_t stream);
+
+/* Current iteration index t (next iteration to run). */
+vegas_status vegas_get_iteration_index(const vegas_ctx* ctx, int64_t* t);
+
+/* Launch configuration of the sampling kernel: blocks of 256 threads;
+ * n_blocks = 0 restores the automatic choice.  Results do not depend on it
+ * beyond FP64 rounding. */
+vegas_status vegas_set_launch(vegas_ctx* ctx, int32_t n_blocks);
+
+/* Kernel timing for benchmarks.  While enabled, each vegas_iterate records
+ * HIP events on its stream before its event kernel, between the event kernel
+ * and the reduction kernel, and after the reduction (at most 1024 calls are
+ * kept).  vegas_timing_read synchronises on the last recorded event, returns
+ * the summed event-kernel and reduction-kernel times in milliseconds and the
+ * number of calls, and clears the record. */
+vegas_status vegas_timing_enable(vegas_ctx* ctx, int32_t enable);
+vegas_status vegas_timing_read(vegas_ctx* ctx, double* sample_ms, double* merge_ms, int64_t* count);
+
+/* Free the host context (the workspace stays the caller's). */
+vegas_status vegas_destroy(vegas_ctx* ctx);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char* vegas_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems, each with its own grid, run together.
+ * Each problem p uses descs[p] (its problem field is the Philox p) and
+ * n_events[p] events per iteration.  One run = n_iter iterations of every
+ * problem; iterations 0..n_adapt-1 refine after themselves and are left out
+ * of the combination, the remaining ones are combined on the frozen grid.
+ * All iterations of all problems are recorded once as a HIP graph at plan
+ * time and replayed by vegas_batch_run (one graph launch).
+ * ------------------------------------------------------------------------- */
+vegas_status vegas_batch_workspace_size(const vegas_desc* descs, const int64_t* n_events,
+                                        int32_t n, size_t* bytes);
+vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const int64_t* n_events,
+                              int32_t n, void* dev_ws, size_t ws_bytes, int32_t n_iter,
+                              int32_t n_adapt, vegas_stream_t stream);
+/* Restart every problem from the uniform grid and t = 0, then run. */
+vegas_status vegas_batch_run(vegas_batch* batch, vegas_stream_t stream);
+/* Results of every problem (host array of n).  Synchronises. */
+vegas_status vegas_batch_results(vegas_batch* batch, vegas_result_t* host_out,
+                                 vegas_stream_t stream);
+/* Edges of problem p (host FP64 [d_p][N_p+1]).  Synchronises. */
+vegas_status vegas_batch_get_edges(vegas_batch* batch, int32_t p, double* host_edges,
+                                   vegas_stream_t stream);
+vegas_status vegas_batch_destroy(vegas_batch* batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEGAS_H */

@@ -1,0 +1,119 @@
+"""ctypes loader for libvegas (the C ABI declared in include/vegas.h).
+
+The library is the in-tree ``libvegas_gfx950.so`` built by ``build.py``.  There
+is no fallback: if it is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvegas_gfx950.so")
+
+VEGAS_OK, VEGAS_EINVAL, VEGAS_ESTATE, VEGAS_EWORKSPACE = 0, -1, -2, -3
+VEGAS_EHIP, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED = -4, -5, -6
+STATUS_NAMES = {0: "VEGAS_OK", -1: "VEGAS_EINVAL", -2: "VEGAS_ESTATE", -3: "VEGAS_EWORKSPACE",
+                -4: "VEGAS_EHIP", -5: "VEGAS_ENONFINITE", -6: "VEGAS_EUNSUPPORTED"}
+
+GAUSS, BIMODAL, GENZ_DISC, GENZ_PEAK = 0, 1, 2, 3
+FP64, FP32_MIXED = 0, 1
+CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE = 1, 2, 3, 4, 8
+
+# every symbol include/vegas.h declares
+EXPORTS = [
+    "vegas_workspace_size", "vegas_init_grid", "vegas_iterate", "vegas_refine", "vegas_result",
+    "vegas_reset_results", "vegas_set_params_device", "vegas_last_iteration_device",
+    "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
+    "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
+    "vegas_get_iteration_index", "vegas_set_launch", "vegas_timing_enable", "vegas_timing_read",
+    "vegas_destroy", "vegas_last_error",
+    "vegas_batch_workspace_size", "vegas_batch_plan", "vegas_batch_run", "vegas_batch_results",
+    "vegas_batch_get_edges", "vegas_batch_destroy",
+]
+
+
+class VegasError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("integrand", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("alpha", ctypes.c_double),
+                ("params", ctypes.POINTER(ctypes.c_double)), ("n_params", ctypes.c_int32),
+                ("problem", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("integral", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("chi2_dof", ctypes.c_double), ("last_integral", ctypes.c_double),
+                ("last_sigma", ctypes.c_double), ("n_iter", ctypes.c_int64),
+                ("n_combined", ctypes.c_int64), ("n_events", ctypes.c_int64),
+                ("n_nonfinite", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvegas (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libvegas is not built ({LIB_PATH} missing): run "
+                           "`python -m paper_2002_12921_amd.build` or __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    P = ctypes.POINTER
+    pd = P(ctypes.c_double)
+    sig = {
+        "vegas_workspace_size": [P(Desc), P(sz)],
+        "vegas_init_grid": [P(vp), P(Desc), vp, sz, vp],
+        "vegas_iterate": [vp, i64, u32, vp],
+        "vegas_refine": [vp, vp],
+        "vegas_result": [vp, P(Result), vp],
+        "vegas_reset_results": [vp, vp],
+        "vegas_set_params_device": [vp, vp, i32, i32, vp],
+        "vegas_last_iteration_device": [vp, vp, vp],
+        "vegas_adjoint": [vp, i64, i64, vp, vp, vp],
+        "vegas_dump_events": [vp, i64, i64, i64, vp, vp],
+        "vegas_get_edges": [vp, pd, vp],
+        "vegas_set_edges": [vp, pd, vp],
+        "vegas_get_iteration": [vp, pd, pd, vp],
+        "vegas_state_size": [vp, P(sz)],
+        "vegas_get_state": [vp, vp, sz, vp],
+        "vegas_set_state": [vp, vp, sz, vp],
+        "vegas_get_iteration_index": [vp, P(i64)],
+        "vegas_set_launch": [vp, i32],
+        "vegas_timing_enable": [vp, i32],
+        "vegas_timing_read": [vp, pd, pd, P(i64)],
+        "vegas_destroy": [vp],
+        "vegas_batch_workspace_size": [P(Desc), P(i64), i32, P(sz)],
+        "vegas_batch_plan": [P(vp), P(Desc), P(i64), i32, vp, sz, i32, i32, vp],
+        "vegas_batch_run": [vp, vp],
+        "vegas_batch_results": [vp, P(Result), vp],
+        "vegas_batch_get_edges": [vp, i32, pd, vp],
+        "vegas_batch_destroy": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.vegas_last_error.argtypes = []
+    L.vegas_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int, where: str) -> int:
+    if status != VEGAS_OK:
+        msg = lib().vegas_last_error().decode(errors="replace")
+        raise VegasError(status, where, msg)
+    return status

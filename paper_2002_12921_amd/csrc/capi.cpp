@@ -1,0 +1,591 @@
+// C ABI of libvegas: argument validation, workspace layout, launches and the
+// host-side bookkeeping of one integration context (see include/vegas.h).
+#include "vegas.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vegas_internal.hpp"
+
+using namespace vegas;
+
+namespace {
+
+thread_local std::string g_err;
+
+vegas_status fail(vegas_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define VEGAS_HIP(expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(VEGAS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int expected_params(int kind, int d)
+{
+    switch (kind) {
+    case VEGAS_GAUSS: return 1 + d;
+    case VEGAS_BIMODAL: return 1 + 2 * d;
+    case VEGAS_GENZ_DISC:
+    case VEGAS_GENZ_PEAK: return 2 * d;
+    }
+    return -1;
+}
+
+vegas_status check_params(int kind, int d, const double* q)
+{
+    for (int k = 0; k < expected_params(kind, d); ++k)
+        if (!std::isfinite(q[k])) return fail(VEGAS_EINVAL, "params[%d] is not finite", k);
+    if (kind == VEGAS_GAUSS || kind == VEGAS_BIMODAL) {
+        if (!(q[0] > 0.0)) return fail(VEGAS_EINVAL, "Gaussian width a must be > 0 (got %g)", q[0]);
+    } else {
+        for (int i = 0; i < d; ++i) {
+            if (!(q[i] > 0.0)) return fail(VEGAS_EINVAL, "Genz c[%d] must be > 0 (got %g)", i, q[i]);
+            if (kind == VEGAS_GENZ_DISC && !(q[d + i] >= 0.0 && q[d + i] < 1.0))
+                return fail(VEGAS_EINVAL, "Genz discontinuous a[%d] must lie in [0,1) (got %g)", i, q[d + i]);
+        }
+    }
+    return VEGAS_OK;
+}
+
+vegas_status check_desc(const vegas_desc* d)
+{
+    if (!d) return fail(VEGAS_EINVAL, "desc is NULL");
+    if (d->dim < 1 || d->dim > kMaxDim) return fail(VEGAS_EINVAL, "dim must be in [1, %d] (got %d)", kMaxDim, d->dim);
+    if (d->n_bins < 2 || d->n_bins > kMaxBins)
+        return fail(VEGAS_EINVAL, "n_bins must be in [2, %d] (got %d)", kMaxBins, d->n_bins);
+    if (d->integrand < VEGAS_GAUSS || d->integrand > VEGAS_GENZ_PEAK)
+        return fail(VEGAS_EINVAL, "unknown integrand %d", d->integrand);
+    if (d->precision != VEGAS_FP64 && d->precision != VEGAS_FP32_MIXED)
+        return fail(VEGAS_EINVAL, "unknown precision %d", d->precision);
+    if (!(d->alpha >= 0.0) || !std::isfinite(d->alpha)) return fail(VEGAS_EINVAL, "alpha must be finite and >= 0");
+    if (d->problem < 0 || d->problem >= (1 << 24)) return fail(VEGAS_EINVAL, "problem must be in [0, 2^24)");
+    const int np = expected_params(d->integrand, d->dim);
+    if (d->n_params != np) return fail(VEGAS_EINVAL, "integrand %d at dim %d takes %d params (got %d)", d->integrand, d->dim, np, d->n_params);
+    if (!d->params) return fail(VEGAS_EINVAL, "params is NULL");
+    const size_t lds = lds_bytes(d->precision == VEGAS_FP64 ? FP64 : FP32, d->dim, d->n_bins) + 64;
+    if (lds > kLdsLimit)
+        return fail(VEGAS_EUNSUPPORTED, "dim*n_bins too large: %zu bytes of LDS per block (limit %zu)", lds, kLdsLimit);
+    return check_params(d->integrand, d->dim, d->params);
+}
+
+}  // namespace
+
+struct vegas_ctx {
+    int d = 0, N = 0, kind = 0, prec = 0, problem = 0;
+    uint64_t seed = 0;
+    double alpha = 1.5;
+    void* ws = nullptr;
+    Layout L{};
+    ProblemPtrs P{};
+    int device = 0;
+    int cu_count = 0;
+    int64_t t = 0;            // next iteration index
+    int rec_idx = 0;          // recorded iterations
+    bool in_chunk = false;
+    int64_t chunk_events = 0; // events already run in the open iteration
+    bool has_hist = false;    // histograms of a finished iteration not yet refined from
+    int blocks_user = 0;
+    int blocks_auto = 0;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> tev;  // 3 per recorded call
+    int n_timed = 0;
+};
+
+namespace {
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t d, N, kind, prec;
+    int64_t t;
+    int32_t rec_idx, has_hist;
+    uint64_t seed;
+};
+constexpr uint32_t kStateMagic = 0x56475331u;  // "VGS1"
+constexpr int kTimedCalls = 1024;
+
+void free_events(vegas_ctx* c)
+{
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
+    c->n_timed = 0;
+}
+
+size_t state_bytes(const vegas_ctx* c)
+{
+    return sizeof(StateHeader) + sizeof(double) * c->d * (c->N + 1) + sizeof(double) * 2 * kMaxRecords +
+           sizeof(int32_t) * kMaxRecords + sizeof(DevResult) + sizeof(double) * c->L.pstride;
+}
+
+int sample_blocks(const vegas_ctx* c, int64_t n)
+{
+    int nb = c->blocks_user > 0 ? c->blocks_user : c->blocks_auto;
+    // at least ~4 events per thread before spreading over more blocks
+    const int64_t want = (n + int64_t(kBlock) * 4 - 1) / (int64_t(kBlock) * 4);
+    if (want < nb) nb = int(want);
+    if (nb < 1) nb = 1;
+    if (nb > kMaxBlocks) nb = kMaxBlocks;
+    return nb;
+}
+
+MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
+{
+    MergeArgs a{};
+    a.partials = c->P.partials;
+    a.level2 = c->P.level2;
+    a.acc = c->P.acc;
+    a.last = c->P.last;
+    a.tickets = c->P.tickets;
+    a.edges = c->P.edges;
+    a.tab64 = c->P.tab64;
+    a.tab32 = c->P.tab32;
+    a.records = c->P.records;
+    a.rec_flag = c->P.rec_flag;
+    a.result = c->P.result;
+    a.alpha = c->alpha;
+    a.M = M;
+    a.rows = rows;
+    int splits = (rows + 63) / 64;
+    if (splits > kMaxSplits) splits = kMaxSplits;
+    if (splits < 1) splits = 1;
+    a.splits = splits;
+    a.d = c->d;
+    a.N = c->N;
+    a.pstride = c->L.pstride;
+    a.flags = flags;
+    a.rec_idx = c->rec_idx;
+    return a;
+}
+
+vegas_status copy_out(vegas_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t s)
+{
+    if (bytes > c->pinned_bytes) return fail(VEGAS_EINVAL, "internal: staging buffer too small");
+    VEGAS_HIP(hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, s));
+    VEGAS_HIP(hipStreamSynchronize(s));
+    std::memcpy(host, c->pinned, bytes);
+    return VEGAS_OK;
+}
+
+vegas_status check_edges(const double* E, int d, int N)
+{
+    for (int i = 0; i < d; ++i) {
+        const double* e = E + size_t(i) * (N + 1);
+        if (e[0] != 0.0 || e[N] != 1.0) return fail(VEGAS_EINVAL, "edges of dim %d must start at 0 and end at 1", i);
+        for (int k = 0; k < N; ++k)
+            if (!(e[k + 1] > e[k])) return fail(VEGAS_EINVAL, "edges of dim %d must increase strictly", i);
+    }
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vegas_last_error(void) { return g_err.c_str(); }
+
+vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes)
+{
+    if (!bytes) return fail(VEGAS_EINVAL, "bytes is NULL");
+    vegas_status st = check_desc(desc);
+    if (st != VEGAS_OK) return st;
+    *bytes = make_layout(desc->dim, desc->n_bins).total;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws, size_t ws_bytes,
+                             vegas_stream_t stream)
+{
+    if (!out) return fail(VEGAS_EINVAL, "out is NULL");
+    *out = nullptr;
+    vegas_status st = check_desc(desc);
+    if (st != VEGAS_OK) return st;
+    const Layout L = make_layout(desc->dim, desc->n_bins);
+    if (!dev_ws) return fail(VEGAS_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0) return fail(VEGAS_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(VEGAS_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    vegas_ctx* c = new (std::nothrow) vegas_ctx();
+    if (!c) return fail(VEGAS_EINVAL, "out of host memory");
+    c->d = desc->dim;
+    c->N = desc->n_bins;
+    c->kind = desc->integrand;
+    c->prec = desc->precision == VEGAS_FP64 ? FP64 : FP32;
+    c->problem = desc->problem;
+    c->seed = desc->seed;
+    c->alpha = desc->alpha;
+    c->ws = dev_ws;
+    c->L = L;
+    c->P = problem_ptrs(dev_ws, L);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto bail = [&](vegas_status e) {
+        if (c->pinned) (void)hipHostFree(c->pinned);
+        delete c;
+        return e;
+    };
+    hipError_t he;
+    if ((he = hipGetDevice(&c->device)) != hipSuccess ||
+        (he = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
+        return bail(fail(VEGAS_EHIP, "device query: %s", hipGetErrorString(he)));
+    const int per_cu = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N);
+    int nb = c->cu_count * per_cu;
+    c->blocks_auto = nb > kMaxBlocks ? kMaxBlocks : (nb < 1 ? 1 : nb);
+    c->pinned_bytes = state_bytes(c) + 4096;
+    if ((he = hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
+        c->pinned = nullptr;
+        return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
+    }
+    const size_t pbytes = sizeof(double) * desc->n_params;
+    if ((he = hipMemcpyAsync(c->P.params, desc->params, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = launch_init_state(c->P, c->d, c->N, c->L.pstride, s)) != hipSuccess ||
+        (he = launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s)) != hipSuccess)
+        return bail(fail(VEGAS_EHIP, "init: %s", hipGetErrorString(he)));
+    *out = c;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40] (got %lld)", (long long)n);
+    if (flags & ~uint32_t(VEGAS_CHUNK_BEGIN | VEGAS_CHUNK_END | VEGAS_NO_COMBINE | VEGAS_REFINE))
+        return fail(VEGAS_EINVAL, "unknown flags 0x%x", flags);
+    const bool begin = flags & VEGAS_CHUNK_BEGIN, end = flags & VEGAS_CHUNK_END;
+    if ((flags & (VEGAS_NO_COMBINE | VEGAS_REFINE)) && !end)
+        return fail(VEGAS_EINVAL, "REFINE / NO_COMBINE only apply with CHUNK_END");
+    if (begin && c->in_chunk) return fail(VEGAS_ESTATE, "CHUNK_BEGIN while an iteration is open");
+    if (!begin && !c->in_chunk) return fail(VEGAS_ESTATE, "no open iteration: start with CHUNK_BEGIN");
+    const int64_t e0 = begin ? 0 : c->chunk_events;
+    const int64_t M = e0 + n;
+    if (M > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "iteration exceeds 2^40 events");
+    if (end && M < 2) return fail(VEGAS_EINVAL, "an iteration needs at least 2 events");
+    if (end && c->rec_idx >= kMaxRecords)
+        return fail(VEGAS_ESTATE, "%d iterations recorded: call vegas_reset_results", kMaxRecords);
+    if (c->t >= (int64_t(1) << 32)) return fail(VEGAS_ESTATE, "iteration index exhausted");
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int blocks = sample_blocks(c, n);
+    SampleArgs a{};
+    a.cst = c->P.cst;
+    a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.partials = c->P.partials;
+    a.e0 = uint64_t(e0);
+    a.n = uint64_t(n);
+    a.t = uint32_t(c->t);
+    a.ctr3 = uint32_t(c->problem) << 8;
+    a.key0 = uint32_t(c->seed);
+    a.key1 = uint32_t(c->seed >> 32);
+    a.d = c->d;
+    a.N = c->N;
+    a.pstride = c->L.pstride;
+    const bool timed = c->timing && c->n_timed < kTimedCalls;
+    if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
+    VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, s));
+    if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
+    int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
+             ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0);
+    VEGAS_HIP(launch_merge(merge_args(c, blocks, mf, double(M)), s));
+    if (timed) {
+        VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 2], s));
+        c->n_timed += 1;
+    }
+
+    c->chunk_events = M;
+    c->in_chunk = !end;
+    if (end) {
+        c->t += 1;
+        c->rec_idx += 1;
+        c->has_hist = !(flags & VEGAS_REFINE);
+        c->chunk_events = 0;
+    }
+    return VEGAS_OK;
+}
+
+vegas_status vegas_refine(vegas_ctx* c, vegas_stream_t stream)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    if (!c->has_hist) return fail(VEGAS_ESTATE, "no completed iteration whose histograms are unused");
+    VEGAS_HIP(launch_refine(merge_args(c, 1, 0, 0.0), static_cast<hipStream_t>(stream)));
+    c->has_hist = false;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_result(vegas_ctx* c, vegas_result_t* out, vegas_stream_t stream)
+{
+    if (!c || !out) return fail(VEGAS_EINVAL, "NULL argument");
+    DevResult R;
+    vegas_status st = copy_out(c, &R, c->P.result, sizeof(R), static_cast<hipStream_t>(stream));
+    if (st != VEGAS_OK) return st;
+    out->integral = R.integral;
+    out->sigma = R.sigma;
+    out->chi2_dof = R.chi2_dof;
+    out->last_integral = R.last_integral;
+    out->last_sigma = std::sqrt(R.last_var);
+    out->n_iter = R.n_iter;
+    out->n_combined = R.n_combined;
+    out->n_events = R.n_events;
+    out->n_nonfinite = R.n_nonfinite;
+    if (R.n_nonfinite > 0) return fail(VEGAS_ENONFINITE, "%lld recorded iteration(s) were not finite", (long long)R.n_nonfinite);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_reset_results(vegas_ctx* c, vegas_stream_t stream)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    VEGAS_HIP(launch_reset_results(c->P.records, c->P.rec_flag, c->P.result, static_cast<hipStream_t>(stream)));
+    c->rec_idx = 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_params_device(vegas_ctx* c, const void* dev_params, int32_t n, int32_t is_fp32,
+                                     vegas_stream_t stream)
+{
+    if (!c || !dev_params) return fail(VEGAS_EINVAL, "NULL argument");
+    if (n != expected_params(c->kind, c->d)) return fail(VEGAS_EINVAL, "expected %d params, got %d", expected_params(c->kind, c->d), n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VEGAS_HIP(launch_params_from(dev_params, n, is_fp32 ? 1 : 0, c->P.params, s));
+    VEGAS_HIP(launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_last_iteration_device(vegas_ctx* c, double* dev_out, vegas_stream_t stream)
+{
+    if (!c || !dev_out) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->rec_idx == 0) return fail(VEGAS_ESTATE, "no recorded iteration");
+    VEGAS_HIP(launch_copy_last(c->P.result, dev_out, static_cast<hipStream_t>(stream)));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const double* dev_gout, double* dev_grad,
+                           vegas_stream_t stream)
+{
+    if (!c || !dev_gout || !dev_grad) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->kind != VEGAS_GAUSS) return fail(VEGAS_EUNSUPPORTED, "the adjoint is implemented for the Gaussian integrand");
+    if (iteration < 0 || iteration >= (int64_t(1) << 32)) return fail(VEGAS_EINVAL, "iteration out of range");
+    if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40]");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    AdjointArgs a{};
+    a.cst = c->P.cst;
+    a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.partials = c->P.adj_part;
+    a.ticket = c->P.tickets + kMaxDim + 1;
+    a.gout = dev_gout;
+    a.grad = dev_grad;
+    a.n = uint64_t(n);
+    a.t = uint32_t(iteration);
+    a.ctr3 = uint32_t(c->problem) << 8;
+    a.key0 = uint32_t(c->seed);
+    a.key1 = uint32_t(c->seed >> 32);
+    a.d = c->d;
+    a.N = c->N;
+    VEGAS_HIP(launch_adjoint(c->prec, a, sample_blocks(c, n), static_cast<hipStream_t>(stream)));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_dump_events(vegas_ctx* c, int64_t iteration, int64_t first, int64_t count, double* dev_out,
+                               vegas_stream_t stream)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (iteration < 0 || iteration >= (int64_t(1) << 32)) return fail(VEGAS_EINVAL, "iteration out of range");
+    if (first < 0 || count < 0 || first + count > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "event range out of bounds");
+    if (count == 0) return VEGAS_OK;
+    if (!dev_out) return fail(VEGAS_EINVAL, "dev_out is NULL");
+    DumpArgs a{};
+    a.cst = c->P.cst;
+    a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.out = dev_out;
+    a.e0 = uint64_t(first);
+    a.n = uint64_t(count);
+    a.t = uint32_t(iteration);
+    a.ctr3 = uint32_t(c->problem) << 8;
+    a.key0 = uint32_t(c->seed);
+    a.key1 = uint32_t(c->seed >> 32);
+    a.d = c->d;
+    a.N = c->N;
+    VEGAS_HIP(launch_dump(c->prec, c->kind, a, static_cast<hipStream_t>(stream)));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_edges(vegas_ctx* c, double* host, vegas_stream_t stream)
+{
+    if (!c || !host) return fail(VEGAS_EINVAL, "NULL argument");
+    return copy_out(c, host, c->P.edges, sizeof(double) * c->d * (c->N + 1), static_cast<hipStream_t>(stream));
+}
+
+vegas_status vegas_set_edges(vegas_ctx* c, const double* host, vegas_stream_t stream)
+{
+    if (!c || !host) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    vegas_status st = check_edges(host, c->d, c->N);
+    if (st != VEGAS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VEGAS_HIP(hipMemcpyAsync(c->P.edges, host, sizeof(double) * c->d * (c->N + 1), hipMemcpyHostToDevice, s));
+    VEGAS_HIP(launch_build_tables(c->P.edges, c->P.tab64, c->P.tab32, c->d, c->N, s));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_iteration(vegas_ctx* c, double* sums, double* hist, vegas_stream_t stream)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (c->rec_idx == 0 && !c->has_hist) return fail(VEGAS_ESTATE, "no completed iteration");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(double) * c->L.pstride;
+    if (bytes > c->pinned_bytes) return fail(VEGAS_EINVAL, "internal: staging buffer too small");
+    VEGAS_HIP(hipMemcpyAsync(c->pinned, c->P.last, bytes, hipMemcpyDeviceToHost, s));
+    VEGAS_HIP(hipStreamSynchronize(s));
+    const double* v = static_cast<const double*>(c->pinned);
+    if (sums) std::memcpy(sums, v, 2 * sizeof(double));
+    if (hist) std::memcpy(hist, v + 2, sizeof(double) * c->d * c->N);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_state_size(const vegas_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return fail(VEGAS_EINVAL, "NULL argument");
+    *bytes = state_bytes(c);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_state(vegas_ctx* c, void* host_buf, size_t bytes, vegas_stream_t stream)
+{
+    if (!c || !host_buf) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    if (bytes < state_bytes(c)) return fail(VEGAS_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, state_bytes(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* p = static_cast<char*>(c->pinned);
+    StateHeader h{kStateMagic, 1u, c->d, c->N, c->kind, c->prec, c->t, c->rec_idx, c->has_hist ? 1 : 0, c->seed};
+    std::memcpy(p, &h, sizeof(h));
+    size_t o = sizeof(h);
+    const size_t eb = sizeof(double) * c->d * (c->N + 1), rb = sizeof(double) * 2 * kMaxRecords,
+                 fb = sizeof(int32_t) * kMaxRecords, lb = sizeof(double) * c->L.pstride;
+    VEGAS_HIP(hipMemcpyAsync(p + o, c->P.edges, eb, hipMemcpyDeviceToHost, s));
+    o += eb;
+    VEGAS_HIP(hipMemcpyAsync(p + o, c->P.records, rb, hipMemcpyDeviceToHost, s));
+    o += rb;
+    VEGAS_HIP(hipMemcpyAsync(p + o, c->P.rec_flag, fb, hipMemcpyDeviceToHost, s));
+    o += fb;
+    VEGAS_HIP(hipMemcpyAsync(p + o, c->P.result, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    o += sizeof(DevResult);
+    VEGAS_HIP(hipMemcpyAsync(p + o, c->P.last, lb, hipMemcpyDeviceToHost, s));
+    o += lb;
+    VEGAS_HIP(hipStreamSynchronize(s));
+    std::memcpy(host_buf, p, o);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_state(vegas_ctx* c, const void* host_buf, size_t bytes, vegas_stream_t stream)
+{
+    if (!c || !host_buf) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    if (bytes < state_bytes(c)) return fail(VEGAS_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, state_bytes(c));
+    StateHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != kStateMagic || h.version != 1u) return fail(VEGAS_EINVAL, "not a vegas state");
+    if (h.d != c->d || h.N != c->N || h.kind != c->kind || h.prec != c->prec || h.seed != c->seed)
+        return fail(VEGAS_EINVAL, "state belongs to a different problem");
+    if (h.rec_idx < 0 || h.rec_idx > kMaxRecords || h.t < 0) return fail(VEGAS_EINVAL, "corrupt state");
+    const char* p = static_cast<const char*>(host_buf) + sizeof(h);
+    if (check_edges(reinterpret_cast<const double*>(p), c->d, c->N) != VEGAS_OK) return VEGAS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t eb = sizeof(double) * c->d * (c->N + 1), rb = sizeof(double) * 2 * kMaxRecords,
+                 fb = sizeof(int32_t) * kMaxRecords, lb = sizeof(double) * c->L.pstride;
+    VEGAS_HIP(hipMemcpyAsync(c->P.edges, p, eb, hipMemcpyHostToDevice, s));
+    p += eb;
+    VEGAS_HIP(hipMemcpyAsync(c->P.records, p, rb, hipMemcpyHostToDevice, s));
+    p += rb;
+    VEGAS_HIP(hipMemcpyAsync(c->P.rec_flag, p, fb, hipMemcpyHostToDevice, s));
+    p += fb;
+    VEGAS_HIP(hipMemcpyAsync(c->P.result, p, sizeof(DevResult), hipMemcpyHostToDevice, s));
+    p += sizeof(DevResult);
+    VEGAS_HIP(hipMemcpyAsync(c->P.last, p, lb, hipMemcpyHostToDevice, s));
+    VEGAS_HIP(launch_build_tables(c->P.edges, c->P.tab64, c->P.tab32, c->d, c->N, s));
+    c->t = h.t;
+    c->rec_idx = h.rec_idx;
+    c->has_hist = h.has_hist != 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_iteration_index(const vegas_ctx* c, int64_t* t)
+{
+    if (!c || !t) return fail(VEGAS_EINVAL, "NULL argument");
+    *t = c->t;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_launch(vegas_ctx* c, int32_t n_blocks)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (n_blocks < 0 || n_blocks > kMaxBlocks) return fail(VEGAS_EINVAL, "n_blocks must be in [0, %d]", kMaxBlocks);
+    c->blocks_user = n_blocks;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_timing_enable(vegas_ctx* c, int32_t enable)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (enable && c->tev.empty()) {
+        c->tev.resize(3 * kTimedCalls);
+        for (auto& e : c->tev) {
+            hipError_t he = hipEventCreate(&e);
+            if (he != hipSuccess) {
+                e = nullptr;
+                c->tev.erase(std::remove(c->tev.begin(), c->tev.end(), nullptr), c->tev.end());
+                free_events(c);
+                return fail(VEGAS_EHIP, "hipEventCreate: %s", hipGetErrorString(he));
+            }
+        }
+    }
+    c->timing = enable != 0;
+    c->n_timed = 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_timing_read(vegas_ctx* c, double* sample_ms, double* merge_ms, int64_t* count)
+{
+    if (!c || !sample_ms || !merge_ms || !count) return fail(VEGAS_EINVAL, "NULL argument");
+    double ts = 0.0, tm = 0.0;
+    if (c->n_timed > 0) {
+        VEGAS_HIP(hipEventSynchronize(c->tev[3 * (c->n_timed - 1) + 2]));
+        for (int k = 0; k < c->n_timed; ++k) {
+            float a = 0.f, b = 0.f;
+            VEGAS_HIP(hipEventElapsedTime(&a, c->tev[3 * k], c->tev[3 * k + 1]));
+            VEGAS_HIP(hipEventElapsedTime(&b, c->tev[3 * k + 1], c->tev[3 * k + 2]));
+            ts += a;
+            tm += b;
+        }
+    }
+    *sample_ms = ts;
+    *merge_ms = tm;
+    *count = c->n_timed;
+    c->n_timed = 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_destroy(vegas_ctx* c)
+{
+    if (!c) return VEGAS_OK;
+    free_events(c);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return VEGAS_OK;
+}
+
+}  // extern "C"

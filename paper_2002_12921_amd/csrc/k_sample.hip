@@ -1,0 +1,279 @@
+// Event kernel of one Vegas iteration: points -> map -> integrand -> block
+// partials of S1 = sum f w, S2 = sum (f w)^2 and H[i][b] = sum (f w)^2 over
+// events in bin b of dimension i (the accumulators of Lepage's method that
+// the paper's per-event stage fills, sec. 2.2).
+//
+// Layout: the grid's (lower edge, width) table [d][N] and the block's
+// histogram [d][N] (FP64) live in LDS; events never touch memory.  Each
+// thread strides over the launch's events; S1/S2 are Kahan-summed per thread,
+// reduced across the block, and each block writes one row
+// (S1, S2, H[d][N]) of the partial table with coalesced stores.
+#include "device_common.hpp"
+
+namespace vegas {
+
+template <class P, int KIND, int DMAX, bool EXACT>
+__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs a)
+{
+    using tab_t = typename P::tab_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int dN = a.d * a.N;
+    const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15);
+    tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    double* hist = reinterpret_cast<double*>(smem + tab_bytes);
+    double* red = hist + dN;
+
+    const tab_t* gtab = static_cast<const tab_t*>(a.tab);
+    for (int k = threadIdx.x; k < dN; k += kBlock) {
+        tab[k] = gtab[k];
+        hist[k] = 0.0;
+    }
+    __syncthreads();
+
+    EvalConsts<P, KIND, DMAX> cst;
+    cst.load(a.cst);
+    const int d = EXACT ? DMAX : a.d;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
+        EventEval<P, KIND, DMAX, EXACT> ev;
+        ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
+        const double v = ev.value(cst);
+        const double v2 = v * v;
+        kahan_add(s1, c1, v);
+        kahan_add(s2, c2, v2);
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i)
+            if (i < d) lds_atomic_add(&(hist + i * a.N)[ev.b[i]], v2);
+    }
+
+    // block_sum synchronises, which also completes every histogram atomic
+    const double S1 = block_sum(s1 - c1, red);
+    const double S2 = block_sum(s2 - c2, red);
+    double* row = a.partials + size_t(blockIdx.x) * a.pstride;
+    if (threadIdx.x == 0) {
+        row[0] = S1;
+        row[1] = S2;
+    }
+    for (int k = threadIdx.x; k < dN; k += kBlock) row[2 + k] = hist[k];
+}
+
+// Per-event records for parity checks: b, delta, x, w, f of each event.
+template <class P, int KIND, int DMAX>
+__global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
+{
+    using tab_t = typename P::tab_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int dN = a.d * a.N;
+    tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    const tab_t* gtab = static_cast<const tab_t*>(a.tab);
+    for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
+    __syncthreads();
+    EvalConsts<P, KIND, DMAX> cst;
+    cst.load(a.cst);
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
+        EventEval<P, KIND, DMAX> ev;
+        ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
+        double* row = a.out + k * size_t(3 * a.d + 2);
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) {
+            if (i < a.d) {
+                row[i] = double(ev.b[i]);
+                row[a.d + i] = double(ev.del[i]);
+                row[2 * a.d + i] = double(ev.x[i]);
+            }
+        }
+        row[3 * a.d] = double(ev.wp) * cst.Cw;
+        row[3 * a.d + 1] = double(ev.F) * cst.Cf;
+    }
+}
+
+// Adjoint at fixed samples (Gaussian): per-thread FP64 sums of
+// v * d ln f / d theta_j, theta = (mu_0..mu_{d-1}, a):
+//   d ln f / d mu_j = 2 (x_j - mu_j) / a^2,  d ln f / d a = (2 s / a^2 - d) / a.
+// Block rows go to a partial table; the last block to finish merges the rows
+// in order and writes gout * sum / M.
+template <class P, int DMAX>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
+{
+    using tab_t = typename P::tab_t;
+    using real = typename P::real;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int dN = a.d * a.N;
+    const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15);
+    tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    double* red = reinterpret_cast<double*>(smem + tab_bytes);
+    const tab_t* gtab = static_cast<const tab_t*>(a.tab);
+    for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
+    __syncthreads();
+
+    const DevConst* c = a.cst;
+    EvalConsts<P, GAUSS, DMAX> cst;
+    cst.load(c);
+    const real ka = P::is64 ? real(c->kexp64) : real(c->ka32);
+    const double inv_a = c->inv_a;
+    double g[DMAX + 1];
+#pragma unroll
+    for (int j = 0; j <= DMAX; ++j) g[j] = 0.0;
+
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
+        EventEval<P, GAUSS, DMAX> ev;
+        ev.run(cst, tab, k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
+        const double v = ev.value(cst);
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            if (j < a.d) {
+                const real dl = real(2) * (ev.x[j] - cst.p1[j]) * ka;
+                g[j] += v * double(dl);
+            }
+        }
+        const real da = real(2) * ev.s * ka - real(a.d);
+        g[DMAX] += v * (double(da) * inv_a);
+    }
+
+    double* row = a.partials + size_t(blockIdx.x) * (a.d + 1);
+#pragma unroll
+    for (int j = 0; j <= DMAX; ++j) {
+        if (j < a.d || j == DMAX) {
+            const double t = block_sum(g[j], red);
+            if (threadIdx.x == 0) row[j < a.d ? j : a.d] = t;
+        }
+    }
+
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) *a.ticket = 0u;
+    const double scale = *a.gout / double(a.n);
+    for (int j = threadIdx.x; j <= a.d; j += kBlock) {
+        double s = 0.0, cc = 0.0;
+        for (unsigned r = 0; r < gridDim.x; ++r) neumaier_add(s, cc, a.partials[size_t(r) * (a.d + 1) + j]);
+        a.grad[j] = (s + cc) * scale;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over (precision, integrand, dimension bucket).
+
+static int dim_bucket(int d)
+{
+    if (d <= 4) return 4;
+    if (d <= 8) return 8;
+    if (d <= 12) return 12;
+    if (d <= 16) return 16;
+    if (d <= 20) return 20;
+    if (d <= 24) return 24;
+    if (d <= 32) return 32;
+    if (d <= 48) return 48;
+    return 64;
+}
+
+#define VEGAS_DMAX_SWITCH(DM, CALL)            \
+    switch (DM) {                              \
+    case 4: { constexpr int D_ = 4; CALL; }    \
+    case 8: { constexpr int D_ = 8; CALL; }    \
+    case 12: { constexpr int D_ = 12; CALL; }  \
+    case 16: { constexpr int D_ = 16; CALL; }  \
+    case 20: { constexpr int D_ = 20; CALL; }  \
+    case 24: { constexpr int D_ = 24; CALL; }  \
+    case 32: { constexpr int D_ = 32; CALL; }  \
+    case 48: { constexpr int D_ = 48; CALL; }  \
+    default: { constexpr int D_ = 64; CALL; }  \
+    }
+
+template <class P, int KIND>
+static const void* sample_fn(int d)
+{
+    if (d == dim_bucket(d)) {
+        VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, true>))
+    }
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, false>))
+}
+
+template <class P>
+static const void* sample_fn_kind(int kind, int d)
+{
+    switch (kind) {
+    case GAUSS: return sample_fn<P, GAUSS>(d);
+    case BIMODAL: return sample_fn<P, BIMODAL>(d);
+    case GENZ_DISC: return sample_fn<P, GENZ_DISC>(d);
+    default: return sample_fn<P, GENZ_PEAK>(d);
+    }
+}
+
+static const void* sample_kernel(int prec, int kind, int d)
+{
+    return prec == FP64 ? sample_fn_kind<P64>(kind, d) : sample_fn_kind<P32>(kind, d);
+}
+
+template <class P, int KIND>
+static const void* dump_fn(int d)
+{
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_dump<P, KIND, D_>))
+}
+
+template <class P>
+static const void* dump_fn_kind(int kind, int d)
+{
+    switch (kind) {
+    case GAUSS: return dump_fn<P, GAUSS>(d);
+    case BIMODAL: return dump_fn<P, BIMODAL>(d);
+    case GENZ_DISC: return dump_fn<P, GENZ_DISC>(d);
+    default: return dump_fn<P, GENZ_PEAK>(d);
+    }
+}
+
+template <class P>
+static const void* adjoint_fn(int d)
+{
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_>))
+}
+
+static size_t sample_lds(int prec, int d, int N)
+{
+    return lds_bytes(prec, d, N) + sizeof(double) * (kBlock / 64);
+}
+
+hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, hipStream_t s)
+{
+    const void* fn = sample_kernel(prec, kind, a.d);
+    void* args[] = {const_cast<SampleArgs*>(&a)};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, sample_lds(prec, a.d, a.N), s);
+}
+
+hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s)
+{
+    const void* fn = prec == FP64 ? dump_fn_kind<P64>(kind, a.d) : dump_fn_kind<P32>(kind, a.d);
+    const size_t lds = size_t(a.d) * a.N * (prec == FP64 ? 16 : 8);
+    uint64_t blocks = (a.n + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks == 0) blocks = 1;
+    void* args[] = {const_cast<DumpArgs*>(&a)};
+    return hipLaunchKernel(fn, dim3(unsigned(blocks)), dim3(kBlock), args, lds, s);
+}
+
+hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_t s)
+{
+    const void* fn = prec == FP64 ? adjoint_fn<P64>(a.d) : adjoint_fn<P32>(a.d);
+    const size_t tab = size_t(a.d) * a.N * (prec == FP64 ? 16 : 8);
+    const size_t lds = ((tab + 15) & ~size_t(15)) + sizeof(double) * (kBlock / 64);
+    void* args[] = {const_cast<AdjointArgs*>(&a)};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, lds, s);
+}
+
+int sample_max_blocks_per_cu(int prec, int kind, int d, int N)
+{
+    int n = 0;
+    const void* fn = sample_kernel(prec, kind, d);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, sample_lds(prec, d, N)) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+}  // namespace vegas

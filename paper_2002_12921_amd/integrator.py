@@ -1,0 +1,178 @@
+"""Python face of libvegas: argument marshalling only.
+
+PyTorch provides the device workspace (one uint8 tensor) and the stream; every
+step of an iteration runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+INTEGRANDS = {"gauss": _lib.GAUSS, "bimodal": _lib.BIMODAL,
+              "genz_disc": _lib.GENZ_DISC, "genz_peak": _lib.GENZ_PEAK}
+PRECISIONS = {"fp64": _lib.FP64, "fp32_mixed": _lib.FP32_MIXED, "mixed": _lib.FP32_MIXED}
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_desc(dim: int, n_bins: int, integrand, params: Sequence[float], precision="fp64",
+              seed: int = 0, alpha: float = 1.5, problem: int = 0):
+    """Returns (Desc, keep-alive params array)."""
+    kind = INTEGRANDS[integrand] if isinstance(integrand, str) else int(integrand)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    d = _lib.Desc(dim, n_bins, kind, prec, seed, alpha,
+                  p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(p), problem)
+    return d, p
+
+
+class Vegas:
+    """One adaptive Vegas integration on the current HIP device."""
+
+    def __init__(self, dim: int, n_bins: int = 50, integrand="gauss",
+                 params: Optional[Sequence[float]] = None, precision="fp64", seed: int = 0,
+                 alpha: float = 1.5, problem: int = 0, device=None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        if params is None:
+            params = [0.1] + [0.5] * dim
+        self.dim, self.n_bins = dim, n_bins
+        self.desc, self._params = make_desc(dim, n_bins, integrand, params, precision, seed,
+                                            alpha, problem)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream
+        L = lib()
+        nbytes = ctypes.c_size_t()
+        check(L.vegas_workspace_size(ctypes.byref(self.desc), ctypes.byref(nbytes)), "workspace_size")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self._ctx = ctypes.c_void_p()
+            check(L.vegas_init_grid(ctypes.byref(self._ctx), ctypes.byref(self.desc),
+                                    ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                    self._s()), "init_grid")
+
+    # -- helpers -----------------------------------------------------------
+    def _s(self):
+        return _stream_handle(self.stream)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().vegas_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the hot path ------------------------------------------------------
+    def iterate(self, n_events: int, refine: bool = False, combine: bool = True,
+                chunk: Optional[str] = None):
+        """One iteration (or one chunk of one: chunk in {"begin", "mid", "end"})."""
+        flags = {None: _lib.ITER_FULL, "begin": _lib.CHUNK_BEGIN, "mid": 0,
+                 "end": _lib.CHUNK_END, "begin_end": _lib.ITER_FULL}[chunk]
+        if flags & _lib.CHUNK_END:
+            if refine:
+                flags |= _lib.REFINE
+            if not combine:
+                flags |= _lib.NO_COMBINE
+        check(lib().vegas_iterate(self._ctx, int(n_events), flags, self._s()), "iterate")
+
+    def refine(self):
+        check(lib().vegas_refine(self._ctx, self._s()), "refine")
+
+    def result(self, allow_nonfinite: bool = False) -> dict:
+        r = _lib.Result()
+        st = lib().vegas_result(self._ctx, ctypes.byref(r), self._s())
+        if not (allow_nonfinite and st == _lib.VEGAS_ENONFINITE):
+            check(st, "result")
+        return r.as_dict()
+
+    def reset_results(self):
+        check(lib().vegas_reset_results(self._ctx, self._s()), "reset_results")
+
+    # -- parameters, adjoint -------------------------------------------------
+    def set_params_device(self, params: torch.Tensor):
+        assert params.is_cuda and params.is_contiguous() and params.dtype in (torch.float32, torch.float64)
+        check(lib().vegas_set_params_device(self._ctx, ctypes.c_void_p(params.data_ptr()), params.numel(),
+                                            1 if params.dtype == torch.float32 else 0, self._s()),
+              "set_params_device")
+
+    def last_iteration_device(self, out: torch.Tensor):
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 2
+        check(lib().vegas_last_iteration_device(self._ctx, ctypes.c_void_p(out.data_ptr()), self._s()),
+              "last_iteration_device")
+
+    def adjoint(self, iteration: int, n_events: int, gout: torch.Tensor, grad: torch.Tensor):
+        assert gout.is_cuda and gout.dtype == torch.float64
+        assert grad.is_cuda and grad.dtype == torch.float64 and grad.numel() >= self.dim + 1
+        check(lib().vegas_adjoint(self._ctx, iteration, n_events, ctypes.c_void_p(gout.data_ptr()),
+                                  ctypes.c_void_p(grad.data_ptr()), self._s()), "adjoint")
+
+    # -- inspection ------------------------------------------------------------
+    @property
+    def iteration_index(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().vegas_get_iteration_index(self._ctx, ctypes.byref(t)), "get_iteration_index")
+        return t.value
+
+    def dump_events(self, first: int, count: int, iteration: Optional[int] = None) -> torch.Tensor:
+        it = self.iteration_index if iteration is None else iteration
+        out = torch.empty((count, 3 * self.dim + 2), dtype=torch.float64, device=self.device)
+        check(lib().vegas_dump_events(self._ctx, it, first, count, ctypes.c_void_p(out.data_ptr()),
+                                      self._s()), "dump_events")
+        return out
+
+    def edges(self) -> np.ndarray:
+        e = np.zeros((self.dim, self.n_bins + 1))
+        check(lib().vegas_get_edges(self._ctx, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    self._s()), "get_edges")
+        return e
+
+    def set_edges(self, edges: np.ndarray):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        assert e.shape == (self.dim, self.n_bins + 1)
+        check(lib().vegas_set_edges(self._ctx, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    self._s()), "set_edges")
+
+    def last_iteration(self):
+        """(S1, S2, H[d, N]) of the last completed iteration."""
+        sums = np.zeros(2)
+        H = np.zeros((self.dim, self.n_bins))
+        P = ctypes.POINTER(ctypes.c_double)
+        check(lib().vegas_get_iteration(self._ctx, sums.ctypes.data_as(P), H.ctypes.data_as(P),
+                                        self._s()), "get_iteration")
+        return sums[0], sums[1], H
+
+    def set_launch(self, n_blocks: int):
+        check(lib().vegas_set_launch(self._ctx, n_blocks), "set_launch")
+
+    def timing_enable(self, enable: bool = True):
+        check(lib().vegas_timing_enable(self._ctx, 1 if enable else 0), "timing_enable")
+
+    def timing_read(self):
+        """(summed event-kernel ms, summed reduction-kernel ms, calls) since the last read."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        check(lib().vegas_timing_read(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+              "timing_read")
+        return a.value, b.value, n.value
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        check(lib().vegas_state_size(self._ctx, ctypes.byref(n)), "state_size")
+        buf = ctypes.create_string_buffer(n.value)
+        check(lib().vegas_get_state(self._ctx, buf, n.value, self._s()), "get_state")
+        return buf.raw
+
+    def set_state(self, state: bytes):
+        buf = ctypes.create_string_buffer(state, len(state))
+        check(lib().vegas_set_state(self._ctx, buf, len(state), self._s()), "set_state")

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/vegas.h declares, and rejects bad arguments before
+making any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2002_12921_amd import _lib
+from paper_2002_12921_amd.integrator import make_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vegas.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vegas_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(_lib.EXPORTS)
+
+
+def _size(desc):
+    n = ctypes.c_size_t()
+    st = _lib.lib().vegas_workspace_size(ctypes.byref(desc), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_valid():
+    d, keep = make_desc(8, 50, "gauss", [0.1] + [0.5] * 8, "fp32_mixed")
+    st, n = _size(d)
+    assert st == 0 and n > 0
+    d2, keep2 = make_desc(20, 100, "bimodal", [0.05] + [1 / 3] * 20 + [2 / 3] * 20, "fp32_mixed")
+    st, n2 = _size(d2)
+    assert st == 0 and n2 > n
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=0), _lib.VEGAS_EINVAL),
+    (dict(dim=65), _lib.VEGAS_EINVAL),
+    (dict(n_bins=1), _lib.VEGAS_EINVAL),
+    (dict(n_bins=256), _lib.VEGAS_EINVAL),
+    (dict(alpha=-1.0), _lib.VEGAS_EINVAL),
+    (dict(alpha=float("nan")), _lib.VEGAS_EINVAL),
+    (dict(params=[0.0] + [0.5] * 4), _lib.VEGAS_EINVAL),          # a = 0
+    (dict(params=[0.1] + [0.5] * 3), _lib.VEGAS_EINVAL),          # wrong count
+    (dict(params=[0.1, 0.5, float("inf"), 0.5, 0.5]), _lib.VEGAS_EINVAL),
+    (dict(problem=1 << 24), _lib.VEGAS_EINVAL),
+    (dict(integrand=7), _lib.VEGAS_EINVAL),
+    (dict(precision=3), _lib.VEGAS_EINVAL),
+])
+def test_workspace_size_rejects(kw, code):
+    base = dict(dim=4, n_bins=50, integrand=0, params=[0.1] + [0.5] * 4, precision=0,
+                seed=0, alpha=1.5, problem=0)
+    base.update(kw)
+    if "params" not in kw and base["dim"] != 4:
+        base["params"] = [0.1] + [0.5] * max(base["dim"], 0)
+    d, keep = make_desc(**base)
+    st, _ = _size(d)
+    assert st == code
+    assert len(_lib.lib().vegas_last_error()) > 0
+
+
+def test_lds_limit_is_unsupported():
+    d, keep = make_desc(64, 255, "gauss", [0.1] + [0.5] * 64, "fp64")
+    st, _ = _size(d)
+    assert st == _lib.VEGAS_EUNSUPPORTED
+
+
+def test_genz_parameter_checks():
+    d, keep = make_desc(2, 50, "genz_disc", [1.0, 1.0, 0.5, 1.0], "fp64")   # a = 1 not < 1
+    assert _size(d)[0] == _lib.VEGAS_EINVAL
+    d, keep = make_desc(2, 50, "genz_peak", [1.0, -2.0, 0.5, 0.5], "fp64")  # c < 0
+    assert _size(d)[0] == _lib.VEGAS_EINVAL
+
+
+def test_init_rejects_before_hip():
+    L = _lib.lib()
+    d, keep = make_desc(4, 50, "gauss", [0.1] + [0.5] * 4)
+    ctx = ctypes.c_void_p()
+    assert L.vegas_init_grid(ctypes.byref(ctx), ctypes.byref(d), None, 0, None) == _lib.VEGAS_EWORKSPACE
+    assert L.vegas_init_grid(ctypes.byref(ctx), ctypes.byref(d), ctypes.c_void_p(4096 + 8), 1 << 30, None) == _lib.VEGAS_EWORKSPACE
+    assert L.vegas_init_grid(ctypes.byref(ctx), ctypes.byref(d), ctypes.c_void_p(4096), 16, None) == _lib.VEGAS_EWORKSPACE
+    bad, keep2 = make_desc(4, 50, "gauss", [0.1] + [0.5] * 3)
+    assert L.vegas_init_grid(ctypes.byref(ctx), ctypes.byref(bad), ctypes.c_void_p(4096), 1 << 30, None) == _lib.VEGAS_EINVAL
+    assert ctx.value is None
+
+
+def test_null_context_calls():
+    L = _lib.lib()
+    r = _lib.Result()
+    assert L.vegas_iterate(None, 10, 3, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_refine(None, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_result(None, ctypes.byref(r), None) == _lib.VEGAS_EINVAL
+    assert L.vegas_destroy(None) == _lib.VEGAS_OK
+    assert L.vegas_batch_destroy(None) == _lib.VEGAS_OK

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same points.
+
+Tolerances (FP64 path 1e-12 relative, FP32-mixed path 1e-6 relative, both
+before error propagation):
+* per-event records: bins exact; FP64 delta exact, x within 4 ulp, w and f to
+  rounding level; FP32 delta is exactly RN32 of the FP64 delta, x/w/f to FP32
+  rounding level;
+* per-iteration sums S1, S2 relative; histograms per dimension normalised by
+  that dimension's total (|dH| <= tol * sum_b H);
+* refinement: the library's new edges against the oracle's refinement of the
+  library's own histograms and edges, absolute;
+* whole runs (FP64): combined integral, error and final edges.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_12921_amd import Vegas
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+def _gauss(d, a=0.1, mu=0.5):
+    mus = [mu] * d if np.isscalar(mu) else list(mu)
+    return [a] + mus
+
+
+def _adapted_edges(d, N, params, kind=oracle.GAUSS, iters=3, n=20000):
+    pr = oracle.Problem(d, N, kind, params)
+    r = oracle.run(pr, oracle.uniform_edges(d, N), iters, n, [1] * iters, [1] * iters)
+    return r["edges"]
+
+
+def _check_events(ev_gpu, ev_or, d, mixed):
+    b_g, b_o = ev_gpu[:, :d], ev_or[:, :d]
+    assert np.array_equal(b_g, b_o), "bins differ"
+    de_g, de_o = ev_gpu[:, d:2 * d], ev_or[:, d:2 * d]
+    x_g, x_o = ev_gpu[:, 2 * d:3 * d], ev_or[:, 2 * d:3 * d]
+    w_g, w_o = ev_gpu[:, 3 * d], ev_or[:, 3 * d]
+    f_g, f_o = ev_gpu[:, 3 * d + 1], ev_or[:, 3 * d + 1]
+    if not mixed:
+        assert np.array_equal(de_g, de_o)
+        assert np.max(np.abs(x_g - x_o)) <= 4 * EPS64
+        assert np.max(np.abs(w_g - w_o) / w_o) <= 4 * d * EPS64
+        big = f_o > 1e-200
+        assert np.max(np.abs(f_g[big] - f_o[big]) / f_o[big]) <= 1e-13
+    else:
+        assert np.array_equal(de_g, de_o.astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(x_g - x_o)) <= 4 * 2.0 ** -24
+        assert np.max(np.abs(w_g - w_o) / w_o) <= (2 * d + 4) * 2.0 ** -24
+        # f: FP32 exponent argument (up to ~|ln f|) carries ~|arg| ulp of error
+        big = f_o > 1e-30
+        arg = np.abs(np.log(np.maximum(f_o[big], 1e-300) / f_o.max()))
+        rel = np.abs(f_g[big] - f_o[big]) / f_o[big]
+        assert np.all(rel <= (8 + 4 * arg) * 2.0 ** -23)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("d,N", [(4, 50), (8, 50), (5, 7), (1, 2), (20, 100), (13, 255)])
+def test_event_records(prec, d, N):
+    params = _gauss(d, 0.1, np.linspace(0.3, 0.7, d))
+    v = Vegas(d, N, "gauss", params, prec, seed=12345)
+    E = _adapted_edges(d, N, params)
+    v.set_edges(E)
+    t, first, count = 3, 1000, 4096 + 37
+    got = v.dump_events(first, count, iteration=t).cpu().numpy()
+    ref = oracle.events(oracle.Problem(d, N, oracle.GAUSS, params, seed=12345), E, t, first, count)
+    _check_events(got, ref, d, prec != "fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kind,params_fn", [
+    ("bimodal", lambda d: [0.05] + [1 / 3] * d + [2 / 3] * d),
+    ("genz_peak", lambda d: list(np.linspace(3, 6, d)) + list(np.linspace(0.2, 0.8, d))),
+    ("genz_disc", lambda d: list(np.linspace(1, 3, d)) + list(np.linspace(0.05, 0.3, d))),
+])
+def test_event_records_other_integrands(prec, kind, params_fn):
+    d, N = 6, 40
+    params = params_fn(d)
+    kid = {"bimodal": oracle.BIMODAL, "genz_peak": oracle.GENZ_PEAK, "genz_disc": oracle.GENZ_DISC}[kind]
+    v = Vegas(d, N, kind, params, prec, seed=7, problem=3)
+    got = v.dump_events(0, 3000, iteration=2).cpu().numpy()
+    ref = oracle.events(oracle.Problem(d, N, kid, params, seed=7, problem=3), oracle.uniform_edges(d, N), 2, 0, 3000)
+    if kind == "genz_disc" and prec != "fp64":
+        # the x_i > a_i decision is taken on the FP32 x: events within FP32
+        # rounding of a threshold may differ; compare the others
+        x_o = ref[:, 2 * d:3 * d]
+        th = np.array(params[d:])
+        near = np.any(np.abs(x_o - th) < 1e-6, axis=1)
+        got, ref = got[~near], ref[~near]
+    _check_events(got, ref, d, prec != "fp64")
+
+
+def _hist_close(Hg, Ho, tol):
+    tot = Ho.sum(axis=1, keepdims=True)
+    return np.all(np.abs(Hg - Ho) <= tol * tot)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
+def test_lockstep_iterations(prec, tol):
+    """Per iteration: sums and histograms vs the oracle on the library's own
+    grid, then the refinement vs the oracle's refinement of the library's
+    histograms."""
+    d, N, M = 8, 50, 200_003
+    params = _gauss(d)
+    v = Vegas(d, N, "gauss", params, prec)
+    pr = oracle.Problem(d, N, oracle.GAUSS, params)
+    for t in range(4):
+        E = v.edges()
+        v.iterate(M)
+        S1, S2, H = v.last_iteration()
+        o1, o2, Ho = oracle.accumulate(pr, E, t, M)
+        assert abs(S1 - o1) <= tol * abs(o1), (t, S1, o1)
+        assert abs(S2 - o2) <= tol * abs(o2), (t, S2, o2)
+        assert _hist_close(H, Ho, tol)
+        v.refine()
+        En = v.edges()
+        assert np.max(np.abs(En - oracle.refine(H, E, 1.5))) <= 1e-12
+        assert np.all(En[:, 0] == 0.0) and np.all(En[:, -1] == 1.0)
+        assert np.all(np.diff(En, axis=1) > 0)
+
+
+def test_free_running_fp64_c1():
+    """Plain FP64 Vegas, d = 4, a = 0.1, 50 bins, 10 iterations x 1e5 events,
+    alpha = 1.5, seed 0, refining after each iteration, all combined."""
+    d, N = 4, 50
+    params = _gauss(d)
+    v = Vegas(d, N, "gauss", params, "fp64")
+    for _ in range(10):
+        v.iterate(100_000, refine=True)
+    r = v.result()
+    ref = oracle.run(oracle.Problem(d, N, oracle.GAUSS, params), oracle.uniform_edges(d, N), 10, 100_000,
+                     [1] * 10, [1] * 10)
+    I, s, c = ref["final"]
+    assert abs(r["integral"] - I) <= 1e-12 * abs(I)
+    assert abs(r["sigma"] - s) <= 1e-12 * s
+    # chi^2 is built from differences I_t - I ~ sigma_t, so it inherits the
+    # 1e-12 relative agreement amplified by I/sigma_t (~1e3)
+    assert abs(r["chi2_dof"] - c) <= 1e-8 * max(c, 1e-3)
+    assert np.max(np.abs(v.edges() - ref["edges"])) <= 1e-12
+    assert r["n_iter"] == 10 and r["n_combined"] == 10 and r["n_events"] == 1_000_000
+    assert abs(r["integral"] - 0.99999999999385016) < 5 * r["sigma"]   # erf(5)^4
+
+
+def test_free_running_c2_shape_reduced():
+    """The C2 schedule (5 adaptation iterations left out of the result, then
+    5 accumulation iterations on the frozen grid) at reduced size, FP64 and
+    mixed: FP64 matches the oracle; mixed drifts by << sigma."""
+    d, N, M = 8, 50, 100_000
+    params = _gauss(d)
+    out = {}
+    for prec in ("fp64", "fp32_mixed"):
+        v = Vegas(d, N, "gauss", params, prec)
+        for _ in range(5):
+            v.iterate(M, refine=True, combine=False)
+        for _ in range(5):
+            v.iterate(M)
+        out[prec] = v.result()
+    ref = oracle.run(oracle.Problem(d, N, oracle.GAUSS, params), oracle.uniform_edges(d, N), 10, M,
+                     [1] * 5 + [0] * 5, [0] * 5 + [1] * 5)
+    I, s, _ = ref["final"]
+    assert abs(out["fp64"]["integral"] - I) <= 1e-12 * I
+    assert abs(out["fp64"]["sigma"] - s) <= 1e-12 * s
+    assert out["fp64"]["n_combined"] == 5
+    assert abs(out["fp32_mixed"]["integral"] - I) <= 0.1 * s
+    assert abs(out["fp32_mixed"]["sigma"] - s) <= 1e-3 * s
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
+def test_chunked_iteration_equals_single_pass(prec, tol):
+    d, N = 6, 60
+    params = _gauss(d, 0.15)
+    E = _adapted_edges(d, N, params)
+    a = Vegas(d, N, "gauss", params, prec)
+    a.set_edges(E)
+    a.iterate(1_000_000)
+    b = Vegas(d, N, "gauss", params, prec)
+    b.set_edges(E)
+    sizes = [123_457, 300_000, 76_543, 250_000, 250_000]
+    b.iterate(sizes[0], chunk="begin")
+    for s in sizes[1:-1]:
+        b.iterate(s, chunk="mid")
+    b.iterate(sizes[-1], chunk="end")
+    sa, sb = a.last_iteration(), b.last_iteration()
+    assert abs(sa[0] - sb[0]) <= 1e-13 * sa[0] and abs(sa[1] - sb[1]) <= 1e-13 * sa[1]
+    assert _hist_close(sb[2], sa[2], 1e-13)
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, oracle.GAUSS, params), E, 0, 1_000_000)
+    assert abs(sb[0] - o1) <= tol * o1 and abs(sb[1] - o2) <= tol * o2
+    assert _hist_close(sb[2], Ho, tol)
+
+
+@pytest.mark.parametrize("M", [2, 3, 255, 256, 257, 1000, 65_537])
+def test_small_and_ragged_sizes(M):
+    d, N = 3, 11
+    params = _gauss(d, 0.2)
+    v = Vegas(d, N, "gauss", params, "fp64", seed=99)
+    v.iterate(M)
+    S1, S2, H = v.last_iteration()
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, oracle.GAUSS, params, seed=99), oracle.uniform_edges(d, N), 0, M)
+    assert abs(S1 - o1) <= 1e-12 * o1 and abs(S2 - o2) <= 1e-12 * o2
+    assert _hist_close(H, Ho, 1e-12)
+    r = v.result()
+    I, var = oracle.iteration_stats(o1, o2, M)
+    assert abs(r["last_integral"] - I) <= 1e-12 * I
+
+
+@pytest.mark.parametrize("d,N,prec", [(1, 2, "fp64"), (64, 50, "fp64"), (64, 100, "fp32_mixed"),
+                                      (33, 255, "fp32_mixed"), (2, 255, "fp64")])
+def test_dimension_and_bin_extremes(d, N, prec):
+    params = _gauss(d, 0.3)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    v = Vegas(d, N, "gauss", params, prec, seed=2**63 + 5)
+    M = 50_000
+    v.iterate(M, refine=True)
+    S1, S2, H = v.last_iteration()
+    pr = oracle.Problem(d, N, oracle.GAUSS, params, seed=2**63 + 5)
+    E0 = oracle.uniform_edges(d, N)
+    o1, o2, Ho = oracle.accumulate(pr, E0, 0, M)
+    assert abs(S1 - o1) <= tol * o1 and abs(S2 - o2) <= tol * o2
+    assert _hist_close(H, Ho, tol)
+    assert np.max(np.abs(v.edges() - oracle.refine(H, E0, 1.5))) <= 1e-12
+
+
+def test_bimodal_d20_streamed_reduced():
+    """The C3 integrand and grid (d = 20, N = 100, a = 0.05 at 1/3 and 2/3),
+    FP32-mixed, one iteration streamed in chunks, at reduced size."""
+    d, N = 20, 100
+    params = [0.05] + [1 / 3] * d + [2 / 3] * d
+    v = Vegas(d, N, "bimodal", params, "fp32_mixed")
+    for k in range(4):
+        v.iterate(50_000, chunk="begin" if k == 0 else ("end" if k == 3 else "mid"), refine=True)
+    S1, S2, H = v.last_iteration()
+    pr = oracle.Problem(d, N, oracle.BIMODAL, params)
+    o1, o2, Ho = oracle.accumulate(pr, oracle.uniform_edges(d, N), 0, 200_000)
+    assert abs(S1 - o1) <= 1e-6 * o1 and abs(S2 - o2) <= 1e-6 * o2
+    assert _hist_close(H, Ho, 1e-6)
+
+
+def test_checkpoint_resume():
+    d, N, M = 5, 30, 40_000
+    params = _gauss(d, 0.12)
+    a = Vegas(d, N, "gauss", params, "fp64", seed=3)
+    for _ in range(3):
+        a.iterate(M, refine=True)
+    st = a.get_state()
+    for _ in range(2):
+        a.iterate(M, refine=True)
+    ra = a.result()
+    b = Vegas(d, N, "gauss", params, "fp64", seed=3)
+    b.set_state(st)
+    assert b.iteration_index == 3
+    for _ in range(2):
+        b.iterate(M, refine=True)
+    rb = b.result()
+    assert abs(ra["integral"] - rb["integral"]) <= 1e-13 * abs(ra["integral"])
+    assert np.max(np.abs(a.edges() - b.edges())) <= 1e-14
+    assert rb["n_iter"] == 5
+
+
+def test_state_errors():
+    from paper_2002_12921_amd._lib import VegasError
+    v = Vegas(3, 10, "gauss", _gauss(3), "fp64")
+    with pytest.raises(VegasError, match="ESTATE"):
+        v.refine()                                  # nothing to refine from
+    with pytest.raises(VegasError, match="ESTATE"):
+        v.iterate(100, chunk="mid")                 # no open iteration
+    v.iterate(100, chunk="begin")
+    with pytest.raises(VegasError, match="ESTATE"):
+        v.iterate(100, chunk="begin")               # already open
+    with pytest.raises(VegasError, match="EINVAL"):
+        v.iterate(0, chunk="end")
+    v.iterate(100, chunk="end")
+    v.refine()
+    with pytest.raises(VegasError, match="ESTATE"):
+        v.refine()                                  # histograms already used
+    r = v.result()
+    assert r["n_iter"] == 1 and r["n_events"] == 200
+
+
+def test_nonfinite_is_reported():
+    # a huge, narrow peak overflows FP32 products in the mixed path? Use an
+    # integrand whose FP64 normalisation overflows: a tiny width in many dims.
+    d = 40
+    v = Vegas(d, 4, "gauss", [1e-9] + [0.5] * d, "fp64")
+    v.iterate(1000)
+    r = v.result(allow_nonfinite=True)
+    assert r["n_nonfinite"] == 1 and r["n_combined"] == 0
+    from paper_2002_12921_amd._lib import VegasError
+    with pytest.raises(VegasError, match="ENONFINITE"):
+        v.result()
