@@ -29,40 +29,50 @@ METRIC = "events/s per Vegas iteration (d=8 Gaussian, 1e7 evts), FP32-mixed vs F
 D, NBINS, A, ALPHA, EVENTS = 8, 50, 0.1, 1.5, 10_000_000
 
 # Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
-# counted in full-rate lane-slots per second.
+# in lane-slots per second (one full-rate wave64 VALU instruction takes four
+# cycles of one SIMD).
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
 def alg_slots_per_event(d: int) -> int:
-    """Algorithmic VALU lane-slots per event of the mixed-precision event
-    kernel (fixed table; wide 32x32->64 multiplies and transcendentals count
-    4 slots, everything else 1):
-      Philox4x32-10: ceil(d/4) calls x 10 rounds x (2 wide mul + 2 three-way xor) = 100 ceil(d/4)
-      binning, exact: 5 per dimension
-      map: convert + fma + LDS address = 3 per dimension
-      integrand: subtract + fma per dimension, + 3 + exp (4)
-      Jacobian: 1 per dimension; sums: 10; histogram address: 1 per dimension
+    """Algorithmic VALU lane-slots per event of the FP32-mixed Gaussian event
+    kernel: the operations the method needs, weighted by gfx950 issue cost
+    (every VALU instruction one slot -- the 32x32->64 multiply-add included,
+    which runs at full rate on gfx950 -- and the FP32 exponential four):
+      Philox4x32-10: ceil(d/4) calls x 10 rounds x (2 multiply-adds + 2 three-way xors) = 40 ceil(d/4)
+      per dimension: binning (multiply-add, convert, fma) 3, map (LDS address,
+        fma, Jacobian multiply) 3, exponent term in FP64 (convert, fma) 2,
+        histogram address 1                                                   = 9 d
+      per event: exponent split and exponential 8, scaling to FP64 4,
+        (f w)^2 and the two compensated sums 9, loop 3                        = 24
+    The LDS atomics of the histograms run on the LDS pipe and are not counted.
     """
-    return 100 * math.ceil(d / 4) + 12 * d + 17
+    return 40 * math.ceil(d / 4) + 9 * d + 24
 
 
 def _events_per_s(ms_per_step: float) -> float:
     return EVENTS / (ms_per_step * 1e-3)
 
 
-def time_path(precision: str, steps: int, warmup: int):
+def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0):
+    """Two timed passes over `steps` adaptation iterations: the first with
+    nothing but the HIP events around the whole region (the headline), the
+    second with the library's per-kernel events (event- and reduction-kernel
+    durations for the roofline)."""
     import torch
     from paper_2002_12921_amd import Vegas
 
     params = [A] + [0.5] * D
     v = Vegas(D, NBINS, "gauss", params, precision, seed=0, alpha=ALPHA)
+    if blocks:
+        v.set_launch(blocks)
+    if replicas:
+        v.set_hist_replicas(replicas)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         v.iterate(EVENTS, refine=True, combine=False)
     torch.cuda.synchronize()
-    v.timing_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
     for _ in range(steps):
@@ -71,6 +81,10 @@ def time_path(precision: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(stop)
+
+    v.timing_enable(True)
+    for _ in range(steps):
+        v.iterate(EVENTS, refine=True, combine=False)
     sample_ms, merge_ms, n = v.timing_read()
     v.timing_enable(False)
     return {
@@ -79,6 +93,7 @@ def time_path(precision: str, steps: int, warmup: int):
         "events_per_s": _events_per_s(total_ms / steps),
         "event_kernel_ms": sample_ms / n,
         "merge_kernel_ms": merge_ms / n,
+        "launch": v.launch_info(),
     }
 
 
@@ -180,10 +195,12 @@ def main():
                      "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
         "merge_kernel_ms": mixed["merge_kernel_ms"],
         "wall_ms_per_step": mixed["wall_ms_per_step"],
+        "launch": mixed["launch"],
     }
     if fp64 is not None:
         out["fp64"] = {"value": fp64["events_per_s"], "ms_per_step": fp64["ms_per_step"],
-                       "event_kernel_ms": fp64["event_kernel_ms"], "merge_kernel_ms": fp64["merge_kernel_ms"]}
+                       "event_kernel_ms": fp64["event_kernel_ms"], "merge_kernel_ms": fp64["merge_kernel_ms"],
+                       "launch": fp64["launch"]}
         out["mixed_over_fp64"] = mixed["events_per_s"] / fp64["events_per_s"]
     if sched:
         m, f = sched["fp32_mixed"], sched["fp64"]

@@ -181,10 +181,22 @@ vegas_status vegas_set_state(vegas_ctx* ctx, const void* host_buf, size_t bytes,
 /* Current iteration index t (next iteration to run). */
 vegas_status vegas_get_iteration_index(const vegas_ctx* ctx, int64_t* t);
 
-/* Launch configuration of the sampling kernel: blocks of 256 threads;
- * n_blocks = 0 restores the automatic choice.  Results do not depend on it
+/* Launch configuration of the event kernel: the number of blocks
+ * (n_blocks = 0 restores the automatic choice).  Results do not depend on it
  * beyond FP64 rounding. */
 vegas_status vegas_set_launch(vegas_ctx* ctx, int32_t n_blocks);
+/* Histogram replicas per bin in the event kernel's LDS (1, 2, 4, 8 or 16;
+ * lane l of a wave adds into replica l mod replicas, so with 16 every lane
+ * has its own LDS bank pair); 0 restores the automatic choice (the most that
+ * fit without losing a resident block).  Results do not depend on it beyond
+ * FP64 rounding. */
+vegas_status vegas_set_hist_replicas(vegas_ctx* ctx, int32_t replicas);
+/* The automatic choice: blocks (compute units x resident blocks per unit),
+ * resident blocks per compute unit, threads per block (1024, 512 or 256,
+ * whichever keeps the most waves resident) and histogram replicas in use.
+ * Any pointer may be NULL. */
+vegas_status vegas_get_launch(const vegas_ctx* ctx, int32_t* auto_blocks, int32_t* blocks_per_cu,
+                              int32_t* threads, int32_t* replicas);
 
 /* Kernel timing for benchmarks.  While enabled, each vegas_iterate records
  * HIP events on its stream before its event kernel, between the event kernel
@@ -220,6 +232,12 @@ vegas_status vegas_batch_run(vegas_batch* batch, vegas_stream_t stream);
 /* Results of every problem (host array of n).  Synchronises. */
 vegas_status vegas_batch_results(vegas_batch* batch, vegas_result_t* host_out,
                                  vegas_stream_t stream);
+/* Schedule chosen at plan time: events per work item (tile), blocks of the
+ * persistent event kernel, number of work items per iteration, and the timed
+ * iteration of the chosen tile during tuning (ms; 0 when the tile was forced
+ * with the environment variable VEGAS_BATCH_TILE).  Any pointer may be NULL. */
+vegas_status vegas_batch_schedule(const vegas_batch* batch, int64_t* tile_events, int32_t* blocks,
+                                  int32_t* n_items, double* tuned_ms);
 /* Edges of problem p (host FP64 [d_p][N_p+1]).  Synchronises. */
 vegas_status vegas_batch_get_edges(vegas_batch* batch, int32_t p, double* host_edges,
                                    vegas_stream_t stream);

@@ -26,10 +26,11 @@ EXPORTS = [
     "vegas_reset_results", "vegas_set_params_device", "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
     "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
-    "vegas_get_iteration_index", "vegas_set_launch", "vegas_timing_enable", "vegas_timing_read",
+    "vegas_get_iteration_index", "vegas_set_launch", "vegas_set_hist_replicas", "vegas_get_launch",
+    "vegas_timing_enable", "vegas_timing_read",
     "vegas_destroy", "vegas_last_error",
     "vegas_batch_workspace_size", "vegas_batch_plan", "vegas_batch_run", "vegas_batch_results",
-    "vegas_batch_get_edges", "vegas_batch_destroy",
+    "vegas_batch_get_edges", "vegas_batch_schedule", "vegas_batch_destroy",
 ]
 
 
@@ -92,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "vegas_set_state": [vp, vp, sz, vp],
         "vegas_get_iteration_index": [vp, P(i64)],
         "vegas_set_launch": [vp, i32],
+        "vegas_get_launch": [vp, P(i32), P(i32), P(i32), P(i32)],
+        "vegas_set_hist_replicas": [vp, i32],
         "vegas_timing_enable": [vp, i32],
         "vegas_timing_read": [vp, pd, pd, P(i64)],
         "vegas_destroy": [vp],
@@ -100,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "vegas_batch_run": [vp, vp],
         "vegas_batch_results": [vp, P(Result), vp],
         "vegas_batch_get_edges": [vp, i32, pd, vp],
+        "vegas_batch_schedule": [vp, P(i64), P(i32), P(i32), pd],
         "vegas_batch_destroy": [vp],
     }
     for name, args in sig.items():

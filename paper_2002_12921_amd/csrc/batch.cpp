@@ -1,10 +1,406 @@
-// placeholder batch entry points
-#include "vegas.h"
-extern "C" {
-vegas_status vegas_batch_workspace_size(const vegas_desc*, const int64_t*, int32_t, size_t*) { return VEGAS_EUNSUPPORTED; }
-vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc*, const int64_t*, int32_t, void*, size_t, int32_t, int32_t, vegas_stream_t) { if (out) *out = nullptr; return VEGAS_EUNSUPPORTED; }
-vegas_status vegas_batch_run(vegas_batch*, vegas_stream_t) { return VEGAS_EUNSUPPORTED; }
-vegas_status vegas_batch_results(vegas_batch*, vegas_result_t*, vegas_stream_t) { return VEGAS_EUNSUPPORTED; }
-vegas_status vegas_batch_get_edges(vegas_batch*, int32_t, double*, vegas_stream_t) { return VEGAS_EUNSUPPORTED; }
-vegas_status vegas_batch_destroy(vegas_batch*) { return VEGAS_OK; }
+// Batch entry points: many independent Vegas integrations run together (see
+// include/vegas.h).  All iterations of all problems are recorded once as a
+// HIP graph and replayed with one graph launch.  The tile size (events per
+// work item, which also fixes events per thread) is chosen at plan time by
+// timing candidate schedules on the batch itself.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "capi_util.hpp"
+#include "vegas_internal.hpp"
+
+using namespace vegas;
+
+namespace {
+
+constexpr int kBatchMaxIter = 1024;
+constexpr int kMaxProblems = 65535;
+const uint64_t kTileCandidates[] = {1u << 13, 1u << 14, 1u << 15, 1u << 16, 1u << 17};
+constexpr uint64_t kTileMin = 1u << 13;
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int dmax_of(int d)
+{
+    if (d <= 4) return 4;
+    if (d <= 8) return 8;
+    if (d <= 16) return 16;
+    if (d <= 32) return 32;
+    return 64;
 }
+
+// Byte layout of a batch workspace.
+struct BatchLayout {
+    size_t probs, items, queue, params, cst, records, rec_flag, results;
+    std::vector<size_t> edges, tab64, tab32, last;  // per problem
+    size_t partials;
+    size_t total;
+    size_t max_items;
+    size_t partial_doubles;
+};
+
+BatchLayout batch_layout(const vegas_desc* descs, const int64_t* n_events, int n)
+{
+    BatchLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = a256(o + bytes); return at; };
+    size_t max_items = 0, pd = 0;
+    for (int p = 0; p < n; ++p) {
+        const size_t it = (size_t(n_events[p]) + kTileMin - 1) / kTileMin;
+        max_items += it;
+        pd += it * size_t(2 + descs[p].dim * descs[p].n_bins);
+    }
+    L.max_items = max_items;
+    L.partial_doubles = pd;
+    L.probs = take(sizeof(BatchProblem) * n);
+    L.items = take(sizeof(BatchItem) * max_items);
+    L.queue = take(256);
+    L.params = take(sizeof(double) * kMaxParams * n);
+    L.cst = take(sizeof(DevConst) * n);
+    L.records = take(sizeof(double) * 2 * kBatchMaxIter * n);
+    L.rec_flag = take(sizeof(int32_t) * kBatchMaxIter * n);
+    L.results = take(sizeof(DevResult) * n);
+    for (int p = 0; p < n; ++p) {
+        const int d = descs[p].dim, N = descs[p].n_bins;
+        L.edges.push_back(take(sizeof(double) * d * (N + 1)));
+        L.tab64.push_back(take(sizeof(double) * 2 * d * N));
+        L.tab32.push_back(take(sizeof(float) * 4 * d * N));
+        L.last.push_back(take(sizeof(double) * (2 + d * N)));
+    }
+    L.partials = take(sizeof(double) * pd);
+    L.total = o;
+    return L;
+}
+
+vegas_status check_batch(const vegas_desc* descs, const int64_t* n_events, int32_t n)
+{
+    if (!descs || !n_events) return fail(VEGAS_EINVAL, "descs / n_events is NULL");
+    if (n < 1 || n > kMaxProblems) return fail(VEGAS_EINVAL, "batch size must be in [1, %d]", kMaxProblems);
+    for (int p = 0; p < n; ++p) {
+        vegas_status st = check_desc(&descs[p]);
+        if (st != VEGAS_OK) return fail(st, "problem %d: %s", p, g_err.c_str());
+        if (descs[p].integrand != descs[0].integrand || descs[p].precision != descs[0].precision)
+            return fail(VEGAS_EINVAL, "problem %d: all problems of a batch share one integrand kind and precision", p);
+        if (n_events[p] < 2 || n_events[p] > (int64_t(1) << 40))
+            return fail(VEGAS_EINVAL, "problem %d: n_events must be in [2, 2^40]", p);
+    }
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+struct vegas_batch {
+    int n = 0, kind = 0, prec = 0, dmax = 0, n_iter = 0, n_adapt = 0;
+    void* ws = nullptr;
+    BatchLayout L;
+    std::vector<BatchProblem> probs;
+    std::vector<int> dims, bins;
+    std::vector<int64_t> events;
+    int blocks = 0;
+    size_t lds = 0;
+    uint64_t tile = 0;
+    int n_items = 0;
+    double tuned_ms = 0.0;
+    hipStream_t priv = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    char* at(size_t off) const { return static_cast<char*>(ws) + off; }
+    BatchArgs args() const
+    {
+        BatchArgs a{};
+        a.probs = reinterpret_cast<const BatchProblem*>(at(L.probs));
+        a.items = reinterpret_cast<const BatchItem*>(at(L.items));
+        a.partials = reinterpret_cast<double*>(at(L.partials));
+        a.queue = reinterpret_cast<uint32_t*>(at(L.queue));
+        a.n_items = n_items;
+        a.n_probs = n;
+        return a;
+    }
+};
+
+namespace {
+
+// Work items for tile size T, in decreasing cost (dimension), then problem,
+// then event order; each problem's items are contiguous, and so are its rows.
+void build_items(vegas_batch* b, uint64_t T, std::vector<BatchItem>& items)
+{
+    std::vector<int> order(b->n);
+    for (int p = 0; p < b->n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->dims[x] > b->dims[y]; });
+    items.clear();
+    uint64_t row = 0;
+    for (int p : order) {
+        BatchProblem& pr = b->probs[p];
+        pr.first_item = int(items.size());
+        pr.row0 = row;
+        const uint64_t M = uint64_t(b->events[p]);
+        for (uint64_t e0 = 0; e0 < M; e0 += T) {
+            BatchItem it{};
+            it.prob = p;
+            it.e0 = e0;
+            it.n = std::min<uint64_t>(T, M - e0);
+            it.row_off = row;
+            row += uint64_t(pr.pstride);
+            items.push_back(it);
+        }
+        pr.n_items = int(items.size()) - pr.first_item;
+    }
+    b->n_items = int(items.size());
+}
+
+vegas_status upload_schedule(vegas_batch* b, uint64_t T)
+{
+    std::vector<BatchItem> items;
+    build_items(b, T, items);
+    if (items.size() > b->L.max_items) return fail(VEGAS_EINVAL, "internal: too many items");
+    VEGAS_HIP(hipMemcpyAsync(b->at(b->L.items), items.data(), sizeof(BatchItem) * items.size(),
+                             hipMemcpyHostToDevice, b->priv));
+    VEGAS_HIP(hipMemcpyAsync(b->at(b->L.probs), b->probs.data(), sizeof(BatchProblem) * b->n,
+                             hipMemcpyHostToDevice, b->priv));
+    VEGAS_HIP(hipStreamSynchronize(b->priv));  // the host vectors go out of scope
+    b->tile = T;
+    return VEGAS_OK;
+}
+
+// One iteration of every problem: persistent event kernel, then the per-problem
+// reduction (records iteration k; refines while k < n_adapt).
+vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s)
+{
+    BatchArgs a = b->args();
+    a.t = uint32_t(k);
+    VEGAS_HIP(launch_batch_sample(b->prec, b->kind, b->dmax, b->lds, a, b->blocks, s));
+    const int flags = k < b->n_adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : 0;
+    VEGAS_HIP(launch_batch_finish(a, b->dmax, b->kind, k, flags, s));
+    return VEGAS_OK;
+}
+
+void destroy_graph(vegas_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+vegas_status vegas_batch_workspace_size(const vegas_desc* descs, const int64_t* n_events, int32_t n, size_t* bytes)
+{
+    if (!bytes) return fail(VEGAS_EINVAL, "bytes is NULL");
+    vegas_status st = check_batch(descs, n_events, n);
+    if (st != VEGAS_OK) return st;
+    *bytes = batch_layout(descs, n_events, n).total;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const int64_t* n_events, int32_t n,
+                              void* dev_ws, size_t ws_bytes, int32_t n_iter, int32_t n_adapt, vegas_stream_t stream)
+{
+    if (!out) return fail(VEGAS_EINVAL, "out is NULL");
+    *out = nullptr;
+    vegas_status st = check_batch(descs, n_events, n);
+    if (st != VEGAS_OK) return st;
+    if (n_iter < 1 || n_iter > kBatchMaxIter) return fail(VEGAS_EINVAL, "n_iter must be in [1, %d]", kBatchMaxIter);
+    if (n_adapt < 0 || n_adapt > n_iter) return fail(VEGAS_EINVAL, "n_adapt must be in [0, n_iter]");
+    const BatchLayout L = batch_layout(descs, n_events, n);
+    if (!dev_ws) return fail(VEGAS_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0) return fail(VEGAS_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(VEGAS_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    vegas_batch* b = new (std::nothrow) vegas_batch();
+    if (!b) return fail(VEGAS_EINVAL, "out of host memory");
+    auto bail = [&](vegas_status e) {
+        destroy_graph(b);
+        if (b->priv) (void)hipStreamDestroy(b->priv);
+        if (b->pinned) (void)hipHostFree(b->pinned);
+        delete b;
+        return e;
+    };
+    b->n = n;
+    b->kind = descs[0].integrand;
+    b->prec = descs[0].precision == VEGAS_FP64 ? FP64 : FP32;
+    b->n_iter = n_iter;
+    b->n_adapt = n_adapt;
+    b->ws = dev_ws;
+    b->L = L;
+    int maxd = 0;
+    size_t lds = 0;
+    for (int p = 0; p < n; ++p) {
+        maxd = std::max(maxd, descs[p].dim);
+        lds = std::max(lds, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins));
+        b->dims.push_back(descs[p].dim);
+        b->bins.push_back(descs[p].n_bins);
+        b->events.push_back(n_events[p]);
+    }
+    b->dmax = dmax_of(maxd);
+    b->lds = lds;
+
+    hipError_t he;
+    int dev = 0, cus = 0;
+    if ((he = hipStreamSynchronize(static_cast<hipStream_t>(stream))) != hipSuccess ||
+        (he = hipGetDevice(&dev)) != hipSuccess ||
+        (he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+        (he = hipStreamCreate(&b->priv)) != hipSuccess)
+        return bail(fail(VEGAS_EHIP, "batch setup: %s", hipGetErrorString(he)));
+    b->blocks = std::max(1, cus * batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds));
+    b->pinned_bytes = sizeof(DevResult) * n + 4096;
+    if ((he = hipHostMalloc(&b->pinned, b->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
+        b->pinned = nullptr;
+        return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
+    }
+
+    // per-problem state and constants
+    b->probs.resize(n);
+    for (int p = 0; p < n; ++p) {
+        const vegas_desc& d = descs[p];
+        BatchProblem& pr = b->probs[p];
+        double* params = reinterpret_cast<double*>(b->at(L.params)) + size_t(p) * kMaxParams;
+        DevConst* cst = reinterpret_cast<DevConst*>(b->at(L.cst)) + p;
+        pr.cst = cst;
+        pr.edges = reinterpret_cast<double*>(b->at(L.edges[p]));
+        pr.tab64 = reinterpret_cast<double2*>(b->at(L.tab64[p]));
+        pr.tab32 = reinterpret_cast<float*>(b->at(L.tab32[p]));
+        pr.last = reinterpret_cast<double*>(b->at(L.last[p]));
+        pr.records = reinterpret_cast<double*>(b->at(L.records)) + size_t(p) * 2 * kBatchMaxIter;
+        pr.rec_flag = reinterpret_cast<int32_t*>(b->at(L.rec_flag)) + size_t(p) * kBatchMaxIter;
+        pr.result = reinterpret_cast<DevResult*>(b->at(L.results)) + p;
+        pr.alpha = d.alpha;
+        pr.M = double(n_events[p]);
+        pr.key0 = uint32_t(d.seed);
+        pr.key1 = uint32_t(d.seed >> 32);
+        pr.ctr3 = uint32_t(d.problem) << 8;
+        pr.d = d.dim;
+        pr.N = d.n_bins;
+        pr.pstride = 2 + d.dim * d.n_bins;
+        if ((he = hipMemcpyAsync(params, d.params, sizeof(double) * d.n_params, hipMemcpyHostToDevice, b->priv)) !=
+                hipSuccess ||
+            (he = launch_prepare(b->prec, b->kind, d.dim, d.n_bins, params, cst, b->priv)) != hipSuccess)
+            return bail(fail(VEGAS_EHIP, "batch prepare: %s", hipGetErrorString(he)));
+    }
+
+    // autotune the tile size: one warm and one timed iteration per candidate
+    const char* forced = std::getenv("VEGAS_BATCH_TILE");
+    uint64_t best = forced ? uint64_t(std::strtoull(forced, nullptr, 10)) : 0;
+    if (best && std::find(std::begin(kTileCandidates), std::end(kTileCandidates), best) == std::end(kTileCandidates))
+        return bail(fail(VEGAS_EINVAL, "VEGAS_BATCH_TILE must be one of 8192 ... 131072"));
+    if (!best) {
+        hipEvent_t e0, e1;
+        if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess)
+            return bail(fail(VEGAS_EHIP, "hipEventCreate: %s", hipGetErrorString(he)));
+        double best_ms = 1e300;
+        for (uint64_t T : kTileCandidates) {
+            if ((st = upload_schedule(b, T)) != VEGAS_OK) return bail(st);
+            BatchArgs a = b->args();
+            if ((he = launch_batch_reset(a, b->dmax, kBatchMaxIter, b->kind, b->priv)) != hipSuccess)
+                return bail(fail(VEGAS_EHIP, "reset: %s", hipGetErrorString(he)));
+            if ((st = enqueue_iteration(b, 0, b->priv)) != VEGAS_OK) return bail(st);
+            (void)hipEventRecord(e0, b->priv);
+            if ((st = enqueue_iteration(b, 1 < n_iter ? 1 : 0, b->priv)) != VEGAS_OK) return bail(st);
+            (void)hipEventRecord(e1, b->priv);
+            if ((he = hipEventSynchronize(e1)) != hipSuccess)
+                return bail(fail(VEGAS_EHIP, "tuning: %s", hipGetErrorString(he)));
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = T;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->tuned_ms = best_ms;
+    }
+    if ((st = upload_schedule(b, best)) != VEGAS_OK) return bail(st);
+
+    // record the whole run: restart, then n_iter iterations
+    if ((he = hipStreamBeginCapture(b->priv, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return bail(fail(VEGAS_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(he)));
+    BatchArgs a = b->args();
+    vegas_status cap = VEGAS_OK;
+    if ((he = launch_batch_reset(a, b->dmax, n_iter, b->kind, b->priv)) != hipSuccess)
+        cap = fail(VEGAS_EHIP, "reset: %s", hipGetErrorString(he));
+    for (int k = 0; k < n_iter && cap == VEGAS_OK; ++k) cap = enqueue_iteration(b, k, b->priv);
+    he = hipStreamEndCapture(b->priv, &b->graph);
+    if (cap != VEGAS_OK) return bail(cap);
+    if (he != hipSuccess) return bail(fail(VEGAS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(he)));
+    if ((he = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return bail(fail(VEGAS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(he)));
+    *out = b;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_run(vegas_batch* b, vegas_stream_t stream)
+{
+    if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    VEGAS_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_results(vegas_batch* b, vegas_result_t* out, vegas_stream_t stream)
+{
+    if (!b || !out) return fail(VEGAS_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VEGAS_HIP(launch_batch_combine(b->args(), b->n_iter, s));
+    VEGAS_HIP(hipMemcpyAsync(b->pinned, b->at(b->L.results), sizeof(DevResult) * b->n, hipMemcpyDeviceToHost, s));
+    VEGAS_HIP(hipStreamSynchronize(s));
+    const DevResult* R = static_cast<const DevResult*>(b->pinned);
+    int64_t bad = 0;
+    for (int p = 0; p < b->n; ++p) {
+        out[p].integral = R[p].integral;
+        out[p].sigma = R[p].sigma;
+        out[p].chi2_dof = R[p].chi2_dof;
+        out[p].last_integral = R[p].last_integral;
+        out[p].last_sigma = std::sqrt(R[p].last_var);
+        out[p].n_iter = R[p].n_iter;
+        out[p].n_combined = R[p].n_combined;
+        out[p].n_events = R[p].n_events;
+        out[p].n_nonfinite = R[p].n_nonfinite;
+        bad += R[p].n_nonfinite;
+    }
+    if (bad) return fail(VEGAS_ENONFINITE, "%lld recorded iteration(s) were not finite", (long long)bad);
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_get_edges(vegas_batch* b, int32_t p, double* host, vegas_stream_t stream)
+{
+    if (!b || !host) return fail(VEGAS_EINVAL, "NULL argument");
+    if (p < 0 || p >= b->n) return fail(VEGAS_EINVAL, "problem %d out of range", p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VEGAS_HIP(hipMemcpyAsync(host, b->at(b->L.edges[p]), sizeof(double) * b->dims[p] * (b->bins[p] + 1),
+                             hipMemcpyDeviceToHost, s));
+    VEGAS_HIP(hipStreamSynchronize(s));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_schedule(const vegas_batch* b, int64_t* tile_events, int32_t* blocks, int32_t* n_items,
+                                  double* tuned_ms)
+{
+    if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    if (tile_events) *tile_events = int64_t(b->tile);
+    if (blocks) *blocks = b->blocks;
+    if (n_items) *n_items = b->n_items;
+    if (tuned_ms) *tuned_ms = b->tuned_ms;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_destroy(vegas_batch* b)
+{
+    if (!b) return VEGAS_OK;
+    destroy_graph(b);
+    if (b->priv) (void)hipStreamDestroy(b->priv);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    delete b;
+    return VEGAS_OK;
+}
+
+}  // extern "C"

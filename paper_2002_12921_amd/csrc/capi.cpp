@@ -11,11 +11,12 @@
 #include <string>
 #include <vector>
 
+#include "capi_util.hpp"
 #include "vegas_internal.hpp"
 
 using namespace vegas;
 
-namespace {
+namespace vegas {
 
 thread_local std::string g_err;
 
@@ -29,12 +30,6 @@ vegas_status fail(vegas_status st, const char* fmt, ...)
     g_err = buf;
     return st;
 }
-
-#define VEGAS_HIP(expr)                                                                      \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess) return fail(VEGAS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 int expected_params(int kind, int d)
 {
@@ -78,13 +73,13 @@ vegas_status check_desc(const vegas_desc* d)
     const int np = expected_params(d->integrand, d->dim);
     if (d->n_params != np) return fail(VEGAS_EINVAL, "integrand %d at dim %d takes %d params (got %d)", d->integrand, d->dim, np, d->n_params);
     if (!d->params) return fail(VEGAS_EINVAL, "params is NULL");
-    const size_t lds = lds_bytes(d->precision == VEGAS_FP64 ? FP64 : FP32, d->dim, d->n_bins) + 64;
+    const size_t lds = lds_bytes(d->precision == VEGAS_FP64 ? FP64 : FP32, d->integrand, d->dim, d->n_bins) + 64;
     if (lds > kLdsLimit)
         return fail(VEGAS_EUNSUPPORTED, "dim*n_bins too large: %zu bytes of LDS per block (limit %zu)", lds, kLdsLimit);
     return check_params(d->integrand, d->dim, d->params);
 }
 
-}  // namespace
+}  // namespace vegas
 
 struct vegas_ctx {
     int d = 0, N = 0, kind = 0, prec = 0, problem = 0;
@@ -102,6 +97,9 @@ struct vegas_ctx {
     bool has_hist = false;    // histograms of a finished iteration not yet refined from
     int blocks_user = 0;
     int blocks_auto = 0;
+    int threads = kBlock;     // threads per block of the event kernel
+    int hrep_log2 = 0;        // histogram replicas (log2) of the event kernel
+    int hrep_user = -1;       // caller's choice (log2), -1 = automatic
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     bool timing = false;
@@ -137,8 +135,8 @@ size_t state_bytes(const vegas_ctx* c)
 int sample_blocks(const vegas_ctx* c, int64_t n)
 {
     int nb = c->blocks_user > 0 ? c->blocks_user : c->blocks_auto;
-    // at least ~4 events per thread before spreading over more blocks
-    const int64_t want = (n + int64_t(kBlock) * 4 - 1) / (int64_t(kBlock) * 4);
+    // at least ~8 events per thread before spreading over more blocks
+    const int64_t want = (n + int64_t(c->threads) * 8 - 1) / (int64_t(c->threads) * 8);
     if (want < nb) nb = int(want);
     if (nb < 1) nb = 1;
     if (nb > kMaxBlocks) nb = kMaxBlocks;
@@ -149,26 +147,22 @@ MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
 {
     MergeArgs a{};
     a.partials = c->P.partials;
-    a.level2 = c->P.level2;
     a.acc = c->P.acc;
     a.last = c->P.last;
-    a.tickets = c->P.tickets;
     a.edges = c->P.edges;
     a.tab64 = c->P.tab64;
     a.tab32 = c->P.tab32;
+    a.cst = c->P.cst;
     a.records = c->P.records;
     a.rec_flag = c->P.rec_flag;
     a.result = c->P.result;
     a.alpha = c->alpha;
     a.M = M;
     a.rows = rows;
-    int splits = (rows + 63) / 64;
-    if (splits > kMaxSplits) splits = kMaxSplits;
-    if (splits < 1) splits = 1;
-    a.splits = splits;
     a.d = c->d;
     a.N = c->N;
     a.pstride = c->L.pstride;
+    a.kind = c->kind;
     a.flags = flags;
     a.rec_idx = c->rec_idx;
     return a;
@@ -243,7 +237,26 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     if ((he = hipGetDevice(&c->device)) != hipSuccess ||
         (he = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "device query: %s", hipGetErrorString(he)));
-    const int per_cu = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N);
+    // block size with the most resident waves per CU (ties: the larger block,
+    // which means fewer partial rows to reduce)
+    int best_waves = 0, per_cu = 1;
+    for (int th : {1024, 512, 256}) {
+        const int bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1);
+        if (bpc * th / 64 > best_waves) {
+            best_waves = bpc * th / 64;
+            per_cu = bpc;
+            c->threads = th;
+        }
+    }
+    // as many histogram replicas (up to 16, one per bank pair) as the LDS
+    // holds without losing a resident block
+    for (int l2 = 4; l2 >= 1; --l2) {
+        if (lds_bytes(c->prec, c->kind, c->d, c->N, 1 << l2) + 256 > kLdsLimit) continue;
+        if (sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, c->threads, 1 << l2) >= per_cu) {
+            c->hrep_log2 = l2;
+            break;
+        }
+    }
     int nb = c->cu_count * per_cu;
     c->blocks_auto = nb > kMaxBlocks ? kMaxBlocks : (nb < 1 ? 1 : nb);
     c->pinned_bytes = state_bytes(c) + 4096;
@@ -254,7 +267,8 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     const size_t pbytes = sizeof(double) * desc->n_params;
     if ((he = hipMemcpyAsync(c->P.params, desc->params, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (he = launch_init_state(c->P, c->d, c->N, c->L.pstride, s)) != hipSuccess ||
-        (he = launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s)) != hipSuccess)
+        (he = launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s)) != hipSuccess ||
+        (he = launch_build_tables(c->P, c->kind, c->d, c->N, s)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "init: %s", hipGetErrorString(he)));
     *out = c;
     return VEGAS_OK;
@@ -296,7 +310,7 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     a.pstride = c->L.pstride;
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
-    VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, s));
+    VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, c->threads, s));
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
     int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
              ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0);
@@ -331,7 +345,9 @@ vegas_status vegas_result(vegas_ctx* c, vegas_result_t* out, vegas_stream_t stre
 {
     if (!c || !out) return fail(VEGAS_EINVAL, "NULL argument");
     DevResult R;
-    vegas_status st = copy_out(c, &R, c->P.result, sizeof(R), static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VEGAS_HIP(launch_combine(c->P.records, c->P.rec_flag, c->rec_idx, c->P.result, s));
+    vegas_status st = copy_out(c, &R, c->P.result, sizeof(R), s);
     if (st != VEGAS_OK) return st;
     out->integral = R.integral;
     out->sigma = R.sigma;
@@ -363,6 +379,7 @@ vegas_status vegas_set_params_device(vegas_ctx* c, const void* dev_params, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     VEGAS_HIP(launch_params_from(dev_params, n, is_fp32 ? 1 : 0, c->P.params, s));
     VEGAS_HIP(launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s));
+    VEGAS_HIP(launch_build_tables(c->P, c->kind, c->d, c->N, s));  // FP32 tables hold centre offsets
     return VEGAS_OK;
 }
 
@@ -386,7 +403,6 @@ vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const dou
     a.cst = c->P.cst;
     a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
     a.partials = c->P.adj_part;
-    a.ticket = c->P.tickets + kMaxDim + 1;
     a.gout = dev_gout;
     a.grad = dev_grad;
     a.n = uint64_t(n);
@@ -438,7 +454,7 @@ vegas_status vegas_set_edges(vegas_ctx* c, const double* host, vegas_stream_t st
     if (st != VEGAS_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     VEGAS_HIP(hipMemcpyAsync(c->P.edges, host, sizeof(double) * c->d * (c->N + 1), hipMemcpyHostToDevice, s));
-    VEGAS_HIP(launch_build_tables(c->P.edges, c->P.tab64, c->P.tab32, c->d, c->N, s));
+    VEGAS_HIP(launch_build_tables(c->P, c->kind, c->d, c->N, s));
     return VEGAS_OK;
 }
 
@@ -476,6 +492,7 @@ vegas_status vegas_get_state(vegas_ctx* c, void* host_buf, size_t bytes, vegas_s
     size_t o = sizeof(h);
     const size_t eb = sizeof(double) * c->d * (c->N + 1), rb = sizeof(double) * 2 * kMaxRecords,
                  fb = sizeof(int32_t) * kMaxRecords, lb = sizeof(double) * c->L.pstride;
+    VEGAS_HIP(launch_combine(c->P.records, c->P.rec_flag, c->rec_idx, c->P.result, s));
     VEGAS_HIP(hipMemcpyAsync(p + o, c->P.edges, eb, hipMemcpyDeviceToHost, s));
     o += eb;
     VEGAS_HIP(hipMemcpyAsync(p + o, c->P.records, rb, hipMemcpyDeviceToHost, s));
@@ -516,7 +533,7 @@ vegas_status vegas_set_state(vegas_ctx* c, const void* host_buf, size_t bytes, v
     VEGAS_HIP(hipMemcpyAsync(c->P.result, p, sizeof(DevResult), hipMemcpyHostToDevice, s));
     p += sizeof(DevResult);
     VEGAS_HIP(hipMemcpyAsync(c->P.last, p, lb, hipMemcpyHostToDevice, s));
-    VEGAS_HIP(launch_build_tables(c->P.edges, c->P.tab64, c->P.tab32, c->d, c->N, s));
+    VEGAS_HIP(launch_build_tables(c->P, c->kind, c->d, c->N, s));
     c->t = h.t;
     c->rec_idx = h.rec_idx;
     c->has_hist = h.has_hist != 0;
@@ -535,6 +552,34 @@ vegas_status vegas_set_launch(vegas_ctx* c, int32_t n_blocks)
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (n_blocks < 0 || n_blocks > kMaxBlocks) return fail(VEGAS_EINVAL, "n_blocks must be in [0, %d]", kMaxBlocks);
     c->blocks_user = n_blocks;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_set_hist_replicas(vegas_ctx* c, int32_t replicas)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (replicas == 0) {
+        c->hrep_user = -1;
+        return VEGAS_OK;
+    }
+    int l2 = 0;
+    while ((1 << l2) < replicas) ++l2;
+    if (replicas < 0 || (1 << l2) != replicas || l2 > 4)
+        return fail(VEGAS_EINVAL, "replicas must be 0 (automatic) or 1, 2, 4, 8, 16");
+    const size_t lds = sample_lds(c->prec, c->kind, c->d, c->N, replicas);
+    if (lds > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "%d replicas need %zu bytes of LDS", replicas, lds);
+    c->hrep_user = l2;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_launch(const vegas_ctx* c, int32_t* auto_blocks, int32_t* blocks_per_cu, int32_t* threads,
+                              int32_t* replicas)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (auto_blocks) *auto_blocks = c->blocks_auto;
+    if (blocks_per_cu) *blocks_per_cu = c->cu_count > 0 ? c->blocks_auto / c->cu_count : 0;
+    if (threads) *threads = c->threads;
+    if (replicas) *replicas = 1 << (c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2);
     return VEGAS_OK;
 }
 

@@ -1,0 +1,27 @@
+// Host-side helpers shared by the single-problem and batch entry points.
+#pragma once
+
+#include <string>
+
+#include "vegas.h"
+
+namespace vegas {
+
+extern thread_local std::string g_err;
+
+// Records a formatted message for vegas_last_error() and returns st.
+vegas_status fail(vegas_status st, const char* fmt, ...);
+
+// Number of integrand parameters of a kind at dimension d (-1: unknown kind).
+int expected_params(int kind, int d);
+
+// Full validation of a problem description (no HIP call).
+vegas_status check_desc(const vegas_desc* d);
+
+}  // namespace vegas
+
+#define VEGAS_HIP(expr)                                                                               \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return vegas::fail(VEGAS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)

@@ -47,30 +47,56 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 }
 
 // ---------------------------------------------------------------------------
-// Precision policies.
+// Precision policies and grid-table entry types.
+//
+// FP64: table entry (E_b, E_{b+1} - E_b); x = E_b + delta * width, u = x - centre.
+// FP32: table entry (RN32(E_b - centre_i), RN32(width) * 2^ws) -- the offset
+//   from the integrand's centre makes u = x - centre carry relative (not
+//   absolute) rounding error, and the power-of-two scaling keeps the width
+//   product near one; delta is pre-scaled by 2^-ws (exact).  The bimodal
+//   integrand has two centres: (E_b - cA, E_b - cB, scaled width, 0).
 struct P64 {
     using real = double;
-    using tab_t = double2;
     static constexpr bool is64 = true;
 };
 struct P32 {
     using real = float;
-    using tab_t = float2;
     static constexpr bool is64 = false;
+};
+
+template <class P, int KIND>
+struct TabEntry {
+    using type = float2;
+};
+template <int KIND>
+struct TabEntry<P64, KIND> {
+    using type = double2;
+};
+template <>
+struct TabEntry<P32, BIMODAL> {
+    using type = float4;
 };
 
 __device__ __forceinline__ double exp_unit(double z) { return exp(z); }  // e^z
 __device__ __forceinline__ float exp2_unit(float z) { return __builtin_amdgcn_exp2f(z); }
 
-// The word k stands for y = (k + 1/2)/2^32.  yN = k N/2^32 + N/2^33 is exact
-// in FP64 (at most 41 significant bits for N < 256), so the bin b = floor(yN)
-// and delta = yN - b are exact: every precision bins every event alike.
-__device__ __forceinline__ void bin_exact(uint32_t k, double nscale, double nhalf, int& b,
-                                          double& delta)
+// The word k stands for y = (k + 1/2)/2^32, so yN = (kN + N/2) / 2^32.  With
+// P = kN + floor(N/2), one 32x32+32 -> 64-bit multiply-add, yN = (P + h)/2^32
+// where h = 1/2 for odd N and 0 for even N; since P + h never reaches the next
+// multiple of 2^32, the bin b = floor(yN) is the high word of P and
+// delta = yN - b = (lo + h) / 2^32, lo the low word.  The bin is exact in
+// every precision; FP64 gets delta exactly, FP32 gets RN32(delta) for even N
+// and delta within one FP32 ulp for odd N.
+struct BinConsts {
+    uint32_t mul, add;  // N, floor(N/2)
+    double h64;         // h / 2^32
+};
+
+__device__ __forceinline__ void bin_words(uint32_t k, const BinConsts& bc, int& b, uint32_t& lo)
 {
-    const double yn = fma(double(k), nscale, nhalf);
-    b = int(yn);                            // truncation == floor for yn >= 0
-    delta = __builtin_amdgcn_fract(yn);     // yn - floor(yn), exact
+    const uint64_t P = uint64_t(k) * bc.mul + bc.add;
+    b = int(uint32_t(P >> 32));
+    lo = uint32_t(P);
 }
 
 // Integrand constants of one problem, read once per thread into registers
@@ -79,21 +105,38 @@ template <class P, int KIND, int DMAX>
 struct EvalConsts {
     using real = typename P::real;
     real p1[DMAX], p2[DMAX];
-    real kexp, wgroup, wlast;
-    double nscale, nhalf, C, Cf, Cw;
+    double c64[DMAX];   // FP32 path, DISC: c_i (the exponent is summed in FP64)
+    real kexp, dscale;
+    double k2;          // FP32 path: log2(e)/a^2 (GAUSS, BIMODAL), log2(e) (DISC)
+    BinConsts bc;
+    float dmul32, dadd32;  // FP32 path: delta * 2^-ws = fma(float(lo), dmul32, dadd32)
+    double C, Cf, Cw;
 
     __device__ __forceinline__ void load(const DevConst* __restrict__ c)
     {
+        // only what the kernel's precision and integrand read (scalar registers are scarce)
 #pragma unroll
         for (int i = 0; i < DMAX; ++i) {
-            p1[i] = P::is64 ? real(c->p1_64[i]) : real(c->p1_32[i]);
-            p2[i] = P::is64 ? real(c->p2_64[i]) : real(c->p2_32[i]);
+            p1[i] = real(0);
+            p2[i] = real(0);
+            c64[i] = 0.0;
+            if constexpr (P::is64) {
+                p1[i] = c->p1_64[i];
+                if constexpr (KIND != GAUSS) p2[i] = c->p2_64[i];
+            } else {
+                if constexpr (KIND == GENZ_PEAK) p1[i] = c->p1_32[i];
+                if constexpr (KIND == GENZ_DISC) c64[i] = c->p1_64[i];
+            }
         }
-        kexp = P::is64 ? real(c->kexp64) : real(c->kexp32);
-        wgroup = real(c->wgroup32);
-        wlast = real(c->wlast32);
-        nscale = c->nscale;
-        nhalf = c->nhalf;
+        kexp = P::is64 ? real(c->kexp64) : real(0);
+        k2 = c->kexp2_64;
+        dscale = real(c->dscale32);
+        const uint32_t N = uint32_t(c->n_bins);
+        bc.mul = N;
+        bc.add = N >> 1;
+        bc.h64 = (N & 1u) ? 0x1p-33 : 0.0;
+        dmul32 = float(c->dscale32) * 0x1p-32f;
+        dadd32 = (N & 1u) ? float(c->dscale32) * 0x1p-33f : 0.0f;
         C = c->C;
         Cf = c->Cf;
         Cw = c->Cw;
@@ -101,20 +144,24 @@ struct EvalConsts {
 };
 
 // Per-event evaluation shared by the sampling, dump and adjoint kernels.
-// Computes, for the event's d uniforms, the bins, map, width product and the
-// unnormalised integrand F; the event value is v = (double)(F*wp) * C.
-// EXACT: d == DMAX, so no per-dimension guards are needed.
+// Computes, for the event's d uniforms, the bins, the offsets u_i = x_i - c_i
+// from the integrand's centres, the width product wp and the integrand's
+// significand F; the event value is v = ldexp(F * wp, ew + fe) * C
+// (FP64: ew = fe = 0).  EXACT: d == DMAX, so no per-dimension guards are needed.
 template <class P, int KIND, int DMAX, bool EXACT = false>
 struct EventEval {
     using real = typename P::real;
-    using tab_t = typename P::tab_t;
+    using tab_t = typename TabEntry<P, KIND>::type;
 
     int b[DMAX];      // bin of each dimension
-    real x[DMAX];     // mapped point
-    real del[DMAX];   // position inside the bin
-    real wp;          // width product (scaled)
-    real F;           // unnormalised integrand
-    real s;           // Gaussian: sum (x_i - mu_i)^2
+    real u[DMAX];     // x_i - centre_i (GAUSS, BIMODAL: mu / muA; DISC, PEAK: a_i)
+    real del[DMAX];   // position inside the bin (FP32: times 2^-ws)
+    real wp;          // width product (FP32: scaled, see ew)
+    real F;           // integrand significand
+    real s;           // GAUSS: sum u_i^2
+    double s64;       // GAUSS: sum u_i^2 as accumulated (FP64 in both paths)
+    int ew;           // FP32: binary exponent taken out of the width product
+    int fe;           // FP32: binary exponent of the integrand (f ~ 2^fe F)
 
     __device__ __forceinline__ void run(const EvalConsts<P, KIND, DMAX>& c, const tab_t* __restrict__ tab,
                                         uint64_t e, uint32_t t, uint32_t ctr3, uint32_t key0,
@@ -122,9 +169,11 @@ struct EventEval {
     {
         const int d = EXACT ? DMAX : d_rt;
         real w = real(1);
-        real sa = real(0), sb = real(0);  // Gaussian / bimodal exponents; DISC: sum c (x-1)
+        real sa = real(0), sb = real(0);  // FP64 path: GAUSS/BIMODAL sums of squares; DISC: sum c u
+        double qa = 0.0, qb = 0.0;        // FP32 path: the same sums, accumulated in FP64
         real den = real(1);               // PEAK: product of denominators
         bool inside = true;               // DISC: all x_i > a_i
+        int ewl = 0;                      // FP32: exponent taken out of w
         const uint32_t elo = uint32_t(e), ehi = uint32_t(e >> 32);
 #pragma unroll
         for (int g = 0; g < DMAX / 4; ++g) {
@@ -135,64 +184,113 @@ struct EventEval {
                     const int i = 4 * g + q;
                     if (i < d) {
                         int bi;
-                        double d64;
-                        bin_exact(k.w[q], c.nscale, c.nhalf, bi, d64);
+                        uint32_t lo;
+                        bin_words(k.w[q], c.bc, bi, lo);
                         b[i] = bi;
                         const tab_t tb = (tab + i * N)[bi];
-                        const real dl = real(d64);
-                        const real xi = fma(dl, tb.y, tb.x);
-                        del[i] = dl;
-                        x[i] = xi;
-                        w *= tb.y;
-                        if constexpr (KIND == GAUSS) {
-                            const real u = xi - c.p1[i];
-                            sa = fma(u, u, sa);
+                        real ui, ubi = real(0), width;
+                        real dl;
+                        if constexpr (P::is64) {
+                            dl = fma(double(lo), 0x1p-32, c.bc.h64);
+                            width = tb.y;
+                            const real xi = fma(dl, tb.y, tb.x);
+                            ui = xi - c.p1[i];
+                            if constexpr (KIND == BIMODAL) ubi = xi - c.p2[i];
+                            if constexpr (KIND == GENZ_DISC || KIND == GENZ_PEAK) ui = xi - c.p2[i];
                         } else if constexpr (KIND == BIMODAL) {
-                            const real u = xi - c.p1[i];
-                            const real v = xi - c.p2[i];
-                            sa = fma(u, u, sa);
-                            sb = fma(v, v, sb);
+                            dl = fmaf(float(lo), c.dmul32, c.dadd32);
+                            width = tb.z;
+                            ui = fma(dl, tb.z, tb.x);
+                            ubi = fma(dl, tb.z, tb.y);
+                        } else {
+                            dl = fmaf(float(lo), c.dmul32, c.dadd32);
+                            width = tb.y;
+                            ui = fma(dl, tb.y, tb.x);
+                        }
+                        del[i] = dl;
+                        u[i] = ui;
+                        w *= width;
+                        if constexpr (KIND == GAUSS) {
+                            if constexpr (P::is64)
+                                sa = fma(ui, ui, sa);
+                            else  // u^2 of an FP32 u is exact in FP64
+                                qa = fma(double(ui), double(ui), qa);
+                        } else if constexpr (KIND == BIMODAL) {
+                            if constexpr (P::is64) {
+                                sa = fma(ui, ui, sa);
+                                sb = fma(ubi, ubi, sb);
+                            } else {
+                                qa = fma(double(ui), double(ui), qa);
+                                qb = fma(double(ubi), double(ubi), qb);
+                            }
                         } else if constexpr (KIND == GENZ_DISC) {
-                            inside = inside && (xi > c.p2[i]);
-                            sa = fma(c.p1[i], xi - real(1), sa);
-                        } else {  // GENZ_PEAK
-                            const real u = xi - c.p2[i];
-                            den *= fma(c.p1[i] * u, u, real(1));
+                            inside = inside && (ui > real(0));
+                            if constexpr (P::is64)
+                                sa = fma(c.p1[i], ui, sa);
+                            else
+                                qa = fma(c.c64[i], double(ui), qa);
+                        } else {  // GENZ_PEAK: c^2 u^2 + 1
+                            den *= fma(c.p1[i] * ui, ui, real(1));
                         }
                     }
                 }
                 if constexpr (!P::is64) {
-                    // keep the FP32 width product near one: exact power-of-two rescale
-                    w *= (4 * g + 4 <= d) ? c.wgroup : c.wlast;
+                    // every 8 dimensions move w's exponent into ew (no FP32 under/overflow)
+                    if ((g & 1) == 1 && 4 * g + 4 < d) {
+                        int e2;
+                        w = frexpf(w, &e2);
+                        ewl += e2;
+                    }
                 }
             }
         }
         wp = w;
         s = sa;
-        if constexpr (KIND == GAUSS) {
-            if constexpr (P::is64)
+        s64 = P::is64 ? double(sa) : qa;
+        ew = ewl;
+        if constexpr (P::is64) {
+            fe = 0;
+            if constexpr (KIND == GAUSS)
                 F = exp_unit(-sa * c.kexp);
-            else
-                F = exp2_unit(-sa * c.kexp);
-        } else if constexpr (KIND == BIMODAL) {
-            if constexpr (P::is64)
+            else if constexpr (KIND == BIMODAL)
                 F = exp_unit(-sa * c.kexp) + exp_unit(-sb * c.kexp);
+            else if constexpr (KIND == GENZ_DISC)
+                F = inside ? exp_unit(sa) : 0.0;  // sa = sum c (x - a)
             else
-                F = exp2_unit(-sa * c.kexp) + exp2_unit(-sb * c.kexp);
-        } else if constexpr (KIND == GENZ_DISC) {
-            // sa = sum c_i (x_i - 1) <= 0 (FP32: already times log2 e)
-            if constexpr (P::is64)
-                F = inside ? exp_unit(sa) : 0.0;
-            else
-                F = inside ? exp2_unit(sa) : 0.0f;
+                F = real(1) / den;
         } else {
-            F = real(1) / den;
+            // FP32 significand, FP64 exponent: with the exponent A (base 2) summed
+            // in FP64, m = floor(A) and F = 2^(m - A) in (1/2, 1] in FP32, so
+            // f = 2^-m F Cf keeps FP64 range
+            s = float(qa);
+            if constexpr (KIND == GAUSS) {
+                const double arg = qa * c.k2;
+                const double m = floor(arg);
+                F = exp2_unit(float(m - arg));
+                fe = -int(m);
+            } else if constexpr (KIND == BIMODAL) {
+                const double aa = qa * c.k2, ab = qb * c.k2;
+                const double m = floor(fmin(aa, ab));
+                F = exp2_unit(float(fmax(m - aa, -200.0))) + exp2_unit(float(fmax(m - ab, -200.0)));
+                fe = -int(m);
+            } else if constexpr (KIND == GENZ_DISC) {
+                const double arg = -qa * c.k2;  // qa = sum c (x - a) >= 0 inside
+                const double m = floor(arg);
+                F = inside ? exp2_unit(float(m - arg)) : 0.0f;
+                fe = -int(m);
+            } else {
+                F = 1.0f / den;
+                fe = 0;
+            }
         }
     }
 
     __device__ __forceinline__ double value(const EvalConsts<P, KIND, DMAX>& c) const
     {
-        return double(F * wp) * c.C;
+        if constexpr (P::is64)
+            return F * wp * c.C;
+        else
+            return ldexp(double(F * wp), ew + fe) * c.C;
     }
 };
 
@@ -214,6 +312,15 @@ __device__ __forceinline__ void kahan_add(double& s, double& c, double v)
     s = t;
 }
 
+// Branch-free compensated step (Knuth's TwoSum): the sum is s + c.
+__device__ __forceinline__ void twosum_add(double& s, double& c, double v)
+{
+    const double t = s + v;
+    const double bp = t - s;
+    c += (s - (t - bp)) + (v - bp);
+    s = t;
+}
+
 // Neumaier step: the sum is s + c.
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double v)
 {
@@ -225,8 +332,8 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double v)
     s = t;
 }
 
-// Block (kBlock threads) sum of one double; result valid in thread 0.
-// red must hold kBlock/64 doubles of LDS.
+// Block sum of one double (blockDim.x a multiple of 64); result valid in
+// thread 0.  red must hold blockDim.x/64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double* red)
 {
     v = wave_sum(v);
@@ -235,11 +342,35 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kBlock / 64; ++k) t += red[k];
+        const int nw = int(blockDim.x) >> 6;
+        for (int k = 0; k < nw; ++k) t += red[k];
     }
     __syncthreads();
     return t;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (lane order).
+__device__ __forceinline__ double wave_inclusive_scan(double v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Running maximum over the 64 lanes of a wave (lane order).
+__device__ __forceinline__ double wave_inclusive_max(double v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(v, off, 64);
+        if (lane >= off) v = fmax(v, o);
+    }
+    return v;
 }
 
 __device__ __forceinline__ void lds_atomic_add(double* p, double v)

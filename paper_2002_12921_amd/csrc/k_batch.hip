@@ -1,2 +1,204 @@
-// placeholder, replaced by the batched persistent kernel
-#include "device_common.hpp"
+// Batched Vegas iterations: many independent problems (own dimension, grid,
+// event count and integrand parameters) in one persistent launch.
+//
+// The event kernel's blocks take work items -- a tile of events of one
+// problem -- from an atomic counter until none is left.  Items are ordered by
+// cost (larger dimension first), so the tail of the launch is made of cheap
+// items.  When a block moves to another problem it reloads that problem's
+// grid table into LDS; each item leaves one partial row (S1, S2, H[d][N]).
+// The finish kernel then reduces each problem's rows (one block per problem
+// and column group), records the iteration and refines the grid, as the
+// single-problem reduction does.
+#include "grid_ops.hpp"
+
+namespace vegas {
+
+template <class P, int KIND, int DMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_sample(BatchArgs a)
+{
+    using tab_t = typename TabEntry<P, KIND>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    __shared__ double red[kBlock / 64];
+    int cur = -1;
+    int d = 0, N = 0, dN = 0;
+    tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    double* hist = nullptr;
+    EvalConsts<P, KIND, DMAX> cst;
+    uint32_t key0 = 0, key1 = 0, ctr3 = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = int(atomicAdd(a.queue, 1u));
+        __syncthreads();
+        const int item = s_item;
+        if (item >= a.n_items) break;  // every block leaves once the queue is empty
+        const BatchItem it = a.items[item];
+        if (it.prob != cur) {
+            cur = it.prob;
+            const BatchProblem& pr = a.probs[cur];
+            d = pr.d;
+            N = pr.N;
+            dN = d * N;
+            key0 = pr.key0;
+            key1 = pr.key1;
+            ctr3 = pr.ctr3;
+            cst.load(pr.cst);
+            const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
+                                        : reinterpret_cast<const tab_t*>(pr.tab32);
+            for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
+            hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15)));
+        }
+        for (int k = threadIdx.x; k < dN; k += kBlock) hist[k] = 0.0;
+        __syncthreads();
+
+        double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+        for (uint64_t k = threadIdx.x; k < it.n; k += kBlock) {
+            EventEval<P, KIND, DMAX> ev;
+            ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
+            const double v = ev.value(cst);
+            const double v2 = v * v;
+            kahan_add(s1, c1, v);
+            kahan_add(s2, c2, v2);
+#pragma unroll
+            for (int i = 0; i < DMAX; ++i)
+                if (i < d) lds_atomic_add(&(hist + i * N)[ev.b[i]], v2);
+        }
+        const double S1 = block_sum(s1 - c1, red);
+        const double S2 = block_sum(s2 - c2, red);
+        double* row = a.partials + it.row_off;
+        if (threadIdx.x == 0) {
+            row[0] = S1;
+            row[1] = S2;
+        }
+        for (int k = threadIdx.x; k < dN; k += kBlock) row[2 + k] = hist[k];
+        __syncthreads();
+    }
+}
+
+// Per problem and column group: reduce the problem's item rows, record the
+// iteration, refine (adaptation iterations).  Also resets the work queue for
+// the next event launch on the stream.
+__global__ __launch_bounds__(kMergeThreads) void k_batch_finish(BatchArgs a, int kind, int rec_idx, int flags)
+{
+    const int g = blockIdx.x, p = blockIdx.y;
+    if (p == 0 && g == 0 && threadIdx.x == 0) *a.queue = 0u;
+    const BatchProblem pr = a.probs[p];
+    if (g > pr.d) return;
+    MergeArgs m{};
+    m.partials = a.partials + pr.row0;
+    m.acc = nullptr;
+    m.last = pr.last;
+    m.edges = pr.edges;
+    m.tab64 = pr.tab64;
+    m.tab32 = pr.tab32;
+    m.cst = pr.cst;
+    m.records = pr.records;
+    m.rec_flag = pr.rec_flag;
+    m.result = pr.result;
+    m.alpha = pr.alpha;
+    m.M = pr.M;
+    m.rows = pr.n_items;
+    m.d = pr.d;
+    m.N = pr.N;
+    m.pstride = pr.pstride;
+    m.kind = kind;
+    m.flags = MERGE_BEGIN | MERGE_END | flags;
+    m.rec_idx = rec_idx;
+    merge_group(m, g);
+}
+
+// Restart every problem: uniform grid and tables, no recorded iterations.
+__global__ __launch_bounds__(kMergeThreads) void k_batch_reset(BatchArgs a, int n_rec, int kind)
+{
+    const int g = blockIdx.x, p = blockIdx.y;
+    if (p == 0 && g == 0 && threadIdx.x == 0) *a.queue = 0u;
+    const BatchProblem pr = a.probs[p];
+    if (g < pr.d) {
+        double* E = pr.edges + size_t(g) * (pr.N + 1);
+        for (int k = threadIdx.x; k <= pr.N; k += blockDim.x) E[k] = double(k) / double(pr.N);
+        __syncthreads();
+        write_tables(g, E, pr.cst, kind, pr.N, pr.tab64, pr.tab32);
+    } else if (g == pr.d) {
+        for (int k = threadIdx.x; k < pr.pstride; k += blockDim.x) pr.last[k] = 0.0;
+        for (int k = threadIdx.x; k < 2 * n_rec; k += blockDim.x) pr.records[k] = 0.0;
+        for (int k = threadIdx.x; k < n_rec; k += blockDim.x) pr.rec_flag[k] = 0;
+        if (threadIdx.x == 0) {
+            const double nan = __builtin_nan("");
+            DevResult* R = pr.result;
+            R->integral = R->sigma = R->chi2_dof = R->last_integral = R->last_var = nan;
+            R->n_iter = R->n_combined = R->n_events = R->n_nonfinite = 0;
+        }
+    }
+}
+
+__global__ void k_batch_combine(BatchArgs a, int n_rec)
+{
+    if (threadIdx.x != 0) return;
+    const BatchProblem pr = a.probs[blockIdx.x];
+    const int n = pr.result->n_iter < n_rec ? int(pr.result->n_iter) : n_rec;
+    combine_records(pr.records, pr.rec_flag, n, pr.result);
+}
+
+hipError_t launch_batch_combine(const BatchArgs& a, int n_rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_combine, dim3(a.n_probs), dim3(64), 0, s, a, n_rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchArgs& a, int dmax, int kind, int rec_idx, int flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_finish, dim3(dmax + 1, a.n_probs), dim3(kMergeThreads), 0, s, a, kind, rec_idx, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(dmax + 1, a.n_probs), dim3(kMergeThreads), 0, s, a, n_rec, kind);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+
+template <class P, int KIND>
+static const void* batch_fn(int dmax)
+{
+    switch (dmax) {
+    case 4: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4>);
+    case 8: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8>);
+    case 16: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16>);
+    case 32: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 32>);
+    default: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 64>);
+    }
+}
+
+template <class P>
+static const void* batch_fn_kind(int kind, int dmax)
+{
+    switch (kind) {
+    case GAUSS: return batch_fn<P, GAUSS>(dmax);
+    case BIMODAL: return batch_fn<P, BIMODAL>(dmax);
+    case GENZ_DISC: return batch_fn<P, GENZ_DISC>(dmax);
+    default: return batch_fn<P, GENZ_PEAK>(dmax);
+    }
+}
+
+static const void* batch_kernel(int prec, int kind, int dmax)
+{
+    return prec == FP64 ? batch_fn_kind<P64>(kind, dmax) : batch_fn_kind<P32>(kind, dmax);
+}
+
+hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
+                               hipStream_t s)
+{
+    void* args[] = {const_cast<BatchArgs*>(&a)};
+    return hipLaunchKernel(batch_kernel(prec, kind, dmax), dim3(blocks), dim3(kBlock), args, lds, s);
+}
+
+int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax), kBlock, lds) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+}  // namespace vegas

@@ -13,29 +13,32 @@
 namespace vegas {
 
 template <class P, int KIND, int DMAX, bool EXACT>
-__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs a)
+// aim for 8 waves per SIMD (two blocks per CU) without spilling; accept 4
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sample(SampleArgs a)
 {
-    using tab_t = typename P::tab_t;
-    extern __shared__ __align__(16) unsigned char smem[];
+    using tab_t = typename TabEntry<P, KIND>::type;
+    extern __shared__ __align__(128) unsigned char smem[];
     const int dN = a.d * a.N;
-    const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15);
+    const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127);
     tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    // histogram [dim][bin][replica]: with 16 replicas every lane of a wave
+    // adds into its own bank pair (lane mod 16), whatever its bin
+    const int rl2 = a.hrep_log2, rep = 1 << rl2;
+    const int lrep = int(threadIdx.x) & (rep - 1);
     double* hist = reinterpret_cast<double*>(smem + tab_bytes);
-    double* red = hist + dN;
+    double* red = hist + dN * rep;
 
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
-    for (int k = threadIdx.x; k < dN; k += kBlock) {
-        tab[k] = gtab[k];
-        hist[k] = 0.0;
-    }
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
+    for (int k = threadIdx.x; k < dN * rep; k += blockDim.x) hist[k] = 0.0;
     __syncthreads();
 
     EvalConsts<P, KIND, DMAX> cst;
     cst.load(a.cst);
     const int d = EXACT ? DMAX : a.d;
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < a.n; k += stride) {
         EventEval<P, KIND, DMAX, EXACT> ev;
         ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
         const double v = ev.value(cst);
@@ -44,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs a)
         kahan_add(s2, c2, v2);
 #pragma unroll
         for (int i = 0; i < DMAX; ++i)
-            if (i < d) lds_atomic_add(&(hist + i * a.N)[ev.b[i]], v2);
+            if (i < d) lds_atomic_add(&(hist + (i * a.N << rl2))[(ev.b[i] << rl2) | lrep], v2);
     }
 
     // block_sum synchronises, which also completes every histogram atomic
@@ -55,14 +58,18 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs a)
         row[0] = S1;
         row[1] = S2;
     }
-    for (int k = threadIdx.x; k < dN; k += kBlock) row[2 + k] = hist[k];
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) {
+        double h = 0.0;
+        for (int r = 0; r < rep; ++r) h += hist[(k << rl2) + r];
+        row[2 + k] = h;
+    }
 }
 
 // Per-event records for parity checks: b, delta, x, w, f of each event.
 template <class P, int KIND, int DMAX>
 __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
 {
-    using tab_t = typename P::tab_t;
+    using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int dN = a.d * a.N;
     tab_t* tab = reinterpret_cast<tab_t*>(smem);
@@ -76,16 +83,17 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
         EventEval<P, KIND, DMAX> ev;
         ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
         double* row = a.out + k * size_t(3 * a.d + 2);
+        // x = centre + u, delta unscaled (exact), w and f with their exponents
 #pragma unroll
         for (int i = 0; i < DMAX; ++i) {
             if (i < a.d) {
                 row[i] = double(ev.b[i]);
-                row[a.d + i] = double(ev.del[i]);
-                row[2 * a.d + i] = double(ev.x[i]);
+                row[a.d + i] = P::is64 ? double(ev.del[i]) : double(ev.del[i] / cst.dscale);
+                row[2 * a.d + i] = double(ev.u[i]) + a.cst->cA64[i];
             }
         }
-        row[3 * a.d] = double(ev.wp) * cst.Cw;
-        row[3 * a.d + 1] = double(ev.F) * cst.Cf;
+        row[3 * a.d] = ldexp(double(ev.wp), ev.ew) * cst.Cw;
+        row[3 * a.d + 1] = ldexp(double(ev.F), ev.fe) * cst.Cf;
     }
 }
 
@@ -97,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
 template <class P, int DMAX>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 {
-    using tab_t = typename P::tab_t;
+    using tab_t = typename TabEntry<P, GAUSS>::type;
     using real = typename P::real;
     extern __shared__ __align__(16) unsigned char smem[];
     const int dN = a.d * a.N;
@@ -113,6 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     cst.load(c);
     const real ka = P::is64 ? real(c->kexp64) : real(c->ka32);
     const double inv_a = c->inv_a;
+    const double ka64 = c->kexp64;
     double g[DMAX + 1];
 #pragma unroll
     for (int j = 0; j <= DMAX; ++j) g[j] = 0.0;
@@ -125,12 +134,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             if (j < a.d) {
-                const real dl = real(2) * (ev.x[j] - cst.p1[j]) * ka;
+                const real dl = real(2) * ev.u[j] * ka;
                 g[j] += v * double(dl);
             }
         }
-        const real da = real(2) * ev.s * ka - real(a.d);
-        g[DMAX] += v * (double(da) * inv_a);
+        const double da = 2.0 * ev.s64 * ka64 - double(a.d);
+        g[DMAX] += v * (da * inv_a);
     }
 
     double* row = a.partials + size_t(blockIdx.x) * (a.d + 1);
@@ -141,19 +150,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
             if (threadIdx.x == 0) row[j < a.d ? j : a.d] = t;
         }
     }
+}
 
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    if (threadIdx.x == 0) *a.ticket = 0u;
+// Final step of the adjoint: block rows added in order (Neumaier), scaled by gout/M.
+__global__ __launch_bounds__(256) void k_adjoint_merge(AdjointArgs a, int rows)
+{
     const double scale = *a.gout / double(a.n);
-    for (int j = threadIdx.x; j <= a.d; j += kBlock) {
+    for (int j = threadIdx.x; j <= a.d; j += blockDim.x) {
         double s = 0.0, cc = 0.0;
-        for (unsigned r = 0; r < gridDim.x; ++r) neumaier_add(s, cc, a.partials[size_t(r) * (a.d + 1) + j]);
+        for (int r = 0; r < rows; ++r) neumaier_add(s, cc, a.partials[size_t(r) * (a.d + 1) + j]);
         a.grad[j] = (s + cc) * scale;
     }
 }
@@ -235,22 +240,23 @@ static const void* adjoint_fn(int d)
     VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_>))
 }
 
-static size_t sample_lds(int prec, int d, int N)
+size_t sample_lds(int prec, int kind, int d, int N, int rep)
 {
-    return lds_bytes(prec, d, N) + sizeof(double) * (kBlock / 64);
+    return lds_bytes(prec, kind, d, N, rep) + sizeof(double) * (kBlock / 64);
 }
 
-hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, hipStream_t s)
+hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, int threads, hipStream_t s)
 {
     const void* fn = sample_kernel(prec, kind, a.d);
     void* args[] = {const_cast<SampleArgs*>(&a)};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, sample_lds(prec, a.d, a.N), s);
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
+                           sample_lds(prec, kind, a.d, a.N, 1 << a.hrep_log2), s);
 }
 
 hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s)
 {
     const void* fn = prec == FP64 ? dump_fn_kind<P64>(kind, a.d) : dump_fn_kind<P32>(kind, a.d);
-    const size_t lds = size_t(a.d) * a.N * (prec == FP64 ? 16 : 8);
+    const size_t lds = size_t(a.d) * a.N * tab_entry_bytes(prec, kind);
     uint64_t blocks = (a.n + kBlock - 1) / kBlock;
     if (blocks > 1024) blocks = 1024;
     if (blocks == 0) blocks = 1;
@@ -261,17 +267,20 @@ hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s)
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_t s)
 {
     const void* fn = prec == FP64 ? adjoint_fn<P64>(a.d) : adjoint_fn<P32>(a.d);
-    const size_t tab = size_t(a.d) * a.N * (prec == FP64 ? 16 : 8);
+    const size_t tab = size_t(a.d) * a.N * tab_entry_bytes(prec, GAUSS);
     const size_t lds = ((tab + 15) & ~size_t(15)) + sizeof(double) * (kBlock / 64);
     void* args[] = {const_cast<AdjointArgs*>(&a)};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, lds, s);
+    hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, lds, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adjoint_merge, dim3(1), dim3(256), 0, s, a, blocks);
+    return hipGetLastError();
 }
 
-int sample_max_blocks_per_cu(int prec, int kind, int d, int N)
+int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int rep)
 {
     int n = 0;
     const void* fn = sample_kernel(prec, kind, d);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, sample_lds(prec, d, N)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, sample_lds(prec, kind, d, N, rep)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

@@ -156,6 +156,15 @@ class Vegas:
     def set_launch(self, n_blocks: int):
         check(lib().vegas_set_launch(self._ctx, n_blocks), "set_launch")
 
+    def launch_info(self) -> dict:
+        a, b, t, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().vegas_get_launch(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t), ctypes.byref(r)),
+              "get_launch")
+        return {"auto_blocks": a.value, "blocks_per_cu": b.value, "threads": t.value, "replicas": r.value}
+
+    def set_hist_replicas(self, replicas: int):
+        check(lib().vegas_set_hist_replicas(self._ctx, replicas), "set_hist_replicas")
+
     def timing_enable(self, enable: bool = True):
         check(lib().vegas_timing_enable(self._ctx, 1 if enable else 0), "timing_enable")
 

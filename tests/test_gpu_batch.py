@@ -1,0 +1,125 @@
+"""GPU parity of the batched path: many problems in one recorded graph.
+
+Each problem of a batch is an independent Vegas run; its points carry the
+problem index in the Philox counter.  FP64 batches match the oracle run of
+each problem (1e-12); FP32-mixed batches match the single-problem mixed path
+on the same points (reduction order only) and the oracle within the mixed
+tolerance.  Graph replays give the same results; the tile size chosen by the
+tuner does not change them beyond reduction-order rounding.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_12921_amd import Vegas
+from paper_2002_12921_amd.batch import VegasBatch
+from paper_2002_12921_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(prec, n=9, seed=7):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for p in range(n):
+        d = int(rng.integers(2, 17))
+        a = float(rng.uniform(0.08, 0.3))
+        probs.append({"dim": d, "n_bins": int(rng.choice([20, 50])), "params": [a] + [0.5] * d,
+                      "n_events": int(rng.integers(5_000, 60_000)), "precision": prec, "problem": 3 * p + 1})
+    return probs
+
+
+def _oracle_run(q, n_iter, n_adapt):
+    pr = oracle.Problem(q["dim"], q["n_bins"], oracle.GAUSS, q["params"], seed=0, problem=q["problem"])
+    return oracle.run(pr, oracle.uniform_edges(q["dim"], q["n_bins"]), n_iter, q["n_events"],
+                      [1] * n_adapt + [0] * (n_iter - n_adapt), [0] * n_adapt + [1] * (n_iter - n_adapt))
+
+
+def test_batch_fp64_matches_oracle():
+    probs = _small_batch("fp64")
+    n_iter, n_adapt = 5, 3
+    b = VegasBatch(probs, n_iter, n_adapt)
+    b.run()
+    res = b.results()
+    for p, q in enumerate(probs):
+        ref = _oracle_run(q, n_iter, n_adapt)
+        I, s, c = ref["final"]
+        assert abs(res[p]["integral"] - I) <= 1e-12 * abs(I), p
+        assert abs(res[p]["sigma"] - s) <= 1e-12 * s, p
+        assert res[p]["n_iter"] == n_iter and res[p]["n_combined"] == n_iter - n_adapt
+        assert np.max(np.abs(b.edges(p) - ref["edges"])) <= 1e-12, p
+
+
+def test_batch_mixed_matches_single_problem_path():
+    probs = _small_batch("fp32_mixed", n=6, seed=11)
+    n_iter, n_adapt = 4, 2
+    b = VegasBatch(probs, n_iter, n_adapt)
+    b.run()
+    res = b.results()
+    for p, q in enumerate(probs):
+        v = Vegas(q["dim"], q["n_bins"], "gauss", q["params"], "fp32_mixed", problem=q["problem"])
+        for k in range(n_iter):
+            v.iterate(q["n_events"], refine=k < n_adapt, combine=k >= n_adapt)
+        r = v.result()
+        # same points and kernels; only reduction order differs (the grids
+        # then differ at rounding level, which the FP32 tables can expose)
+        assert abs(res[p]["integral"] - r["integral"]) <= 1e-10 * abs(r["integral"]), p
+        assert abs(res[p]["sigma"] - r["sigma"]) <= 1e-9 * r["sigma"], p
+        ref = _oracle_run(q, n_iter, n_adapt)
+        I, s, _ = ref["final"]
+        assert abs(res[p]["integral"] - I) <= 0.1 * s, p
+
+
+def test_graph_replay_and_tile_independence(monkeypatch):
+    probs = _small_batch("fp64", n=5, seed=3)
+    b = VegasBatch(probs, 3, 2)
+    b.run()
+    r1 = b.results()
+    b.run()
+    r2 = b.results()
+    for x, y in zip(r1, r2):
+        assert abs(x["integral"] - y["integral"]) <= 1e-13 * abs(x["integral"])
+    tile = b.schedule()["tile_events"]
+    other = 8192 if tile != 8192 else 131072
+    monkeypatch.setenv("VEGAS_BATCH_TILE", str(other))
+    c = VegasBatch(probs, 3, 2)
+    assert c.schedule()["tile_events"] == other
+    c.run()
+    r3 = c.results()
+    for x, y in zip(r1, r3):
+        assert abs(x["integral"] - y["integral"]) <= 1e-12 * abs(x["integral"])
+
+
+def test_batch256_shape_sampled():
+    """The 256-problem batch (d in 2..16, a in [0.05, 0.3], events
+    log-uniform in [1e4, 1e7], 5 adaptation + 5 accumulation iterations,
+    FP32-mixed): every result is finite and near its closed form, and the
+    smallest problems match the oracle run of the same problem."""
+    from scipy import special
+    probs = workloads.batch256()
+    b = VegasBatch(probs, 10, 5)
+    b.run()
+    res = b.results()
+    assert len(res) == 256
+    pulls = []
+    for p, q in enumerate(probs):
+        a, d = q["params"][0], q["dim"]
+        exact = special.erf(0.5 / a) ** d
+        assert np.isfinite(res[p]["integral"]) and res[p]["n_combined"] == 5
+        pulls.append((res[p]["integral"] - exact) / res[p]["sigma"])
+    pulls = np.array(pulls)
+    # a narrow peak in many dimensions seen by few events can make Vegas lock
+    # onto the wrong region (a property of the method, checked below against
+    # the oracle); the bulk of the problems land within 5 sigma
+    assert np.mean(np.abs(pulls) < 5) > 0.9
+    order = list(np.argsort([q["n_events"] for q in probs])[:4])
+    worst = int(np.argmax(np.abs(pulls)))
+    if probs[worst]["n_events"] <= 2_000_000:
+        order.append(worst)
+    for p in order:
+        q = dict(probs[p])
+        ref = _oracle_run(q, 10, 5)
+        I, s, _ = ref["final"]
+        assert abs(res[p]["integral"] - I) <= 0.1 * s, (p, res[p]["integral"], I, s)
