@@ -308,6 +308,7 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     a.d = c->d;
     a.N = c->N;
     a.pstride = c->L.pstride;
+    a.hrep_log2 = c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2;
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
     VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, c->threads, s));
