@@ -16,9 +16,11 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -50,8 +52,61 @@ def alg_slots_per_event(d: int) -> int:
     return 40 * math.ceil(d / 4) + 9 * d + 24
 
 
+# Counter summary of the event kernel (HBM bytes per launch from FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a plain copy of known size).  It
+# holds for the kernel built from these sources only.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_gauss_d8_1e7_mixed_pmc.md")
+KERNEL_SOURCES = ("k_sample.hip", "device_common.hpp", "vegas_internal.hpp")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_12921_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, note): the counter-derived HBM traffic of the event
+    kernel, or None when there is no summary or the kernel changed since."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None, "no counter summary"
+    vals = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None, "kernel changed since the counters were taken"
+    return float(vals["traffic_bytes_per_launch"]), (
+        f"FETCH_SIZE x {vals['fetch_scale']} + WRITE_SIZE x {vals['write_scale']} (copy-calibrated), "
+        f"{os.path.relpath(PMC_SUMMARY, ROOT)}")
+
+
 def _events_per_s(ms_per_step: float) -> float:
     return EVENTS / (ms_per_step * 1e-3)
+
+
+def time_accumulation(precision: str, steps: int, warmup: int):
+    """Accumulation iterations on a frozen (adapted) grid: no histograms and
+    no refinement, the rest of the path as in the adaptation step."""
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
+    for _ in range(5):
+        v.iterate(EVENTS, refine=True, combine=False)
+    for _ in range(warmup):
+        v.iterate(EVENTS, hist=False)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        v.iterate(EVENTS, hist=False)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    return {"ms_per_iteration": ms, "events_per_s": _events_per_s(ms)}
 
 
 def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0):
@@ -99,7 +154,7 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
 
 def c2_schedule(precision: str):
     """5 adaptation iterations (refined after, left out of the result), then
-    5 accumulation iterations on the frozen grid, 1e7 events each."""
+    5 accumulation iterations on the frozen grid (no histograms), 1e7 events each."""
     import torch
     from paper_2002_12921_amd import Vegas
 
@@ -109,11 +164,56 @@ def c2_schedule(precision: str):
     for _ in range(5):
         v.iterate(EVENTS, refine=True, combine=False)
     for _ in range(5):
-        v.iterate(EVENTS)
+        v.iterate(EVENTS, hist=False)
     r = v.result()
     wall = time.perf_counter() - t0
     return {"integral": r["integral"], "sigma": r["sigma"], "chi2_dof": r["chi2_dof"],
             "rel_err": r["sigma"] / r["integral"], "wall_ms": wall * 1e3}
+
+
+def batch_c5(reps: int):
+    """The 256-problem batch (d in 2..16, a in [0.05, 0.3], events log-uniform
+    in [1e4, 1e7], 50 bins, FP32-mixed), 5 adaptation + 5 accumulation
+    iterations per problem, as one recorded graph replayed `reps` times; beside
+    it the same problems run one after another through the single-problem
+    entry points."""
+    import torch
+    from paper_2002_12921_amd import Vegas, workloads
+    from paper_2002_12921_amd.batch import VegasBatch
+
+    probs = workloads.batch256()
+    n_iter, n_adapt = 10, 5
+    total = n_iter * sum(q["n_events"] for q in probs)
+    b = VegasBatch(probs, n_iter, n_adapt)
+    b.run()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.run()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    res = b.results()
+    sched = b.schedule()
+    b.close()
+
+    ctxs = [Vegas(q["dim"], q["n_bins"], "gauss", q["params"], q["precision"], seed=q["seed"],
+                  alpha=q["alpha"], problem=q["problem"]) for q in probs]
+    torch.cuda.synchronize()
+    start.record()
+    for v, q in zip(ctxs, probs):
+        for _ in range(n_adapt):
+            v.iterate(q["n_events"], refine=True, combine=False)
+        for _ in range(n_iter - n_adapt):
+            v.iterate(q["n_events"])
+    stop.record()
+    torch.cuda.synchronize()
+    seq_ms = start.elapsed_time(stop)
+    return {"events_per_s": total / (ms * 1e-3), "ms_per_run": ms, "events_per_run": total,
+            "tile_events": sched["tile_events"], "blocks": sched["blocks"], "n_items": sched["n_items"],
+            "sequential_ms": seq_ms, "batch_over_sequential": seq_ms / ms,
+            "finite_results": int(sum(1 for r in res if math.isfinite(r["integral"])))}
 
 
 def cpu_baseline(iters: int):
@@ -154,6 +254,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--mixed-only", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path is "
@@ -169,11 +270,15 @@ def main():
     mixed = time_path("fp32_mixed", args.steps, args.warmup)
     fp64 = None if args.mixed_only else time_path("fp64", args.steps, args.warmup)
     sched = {} if args.mixed_only else {p: c2_schedule(p) for p in ("fp32_mixed", "fp64")}
+    batch = None if args.mixed_only or args.batch_reps <= 0 else batch_c5(args.batch_reps)
+    accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
+                                          for p in ("fp32_mixed", "fp64")}
 
     slots = alg_slots_per_event(D)
     t_k = mixed["event_kernel_ms"] * 1e-3
     achieved = slots * EVENTS / t_k / 1e12
     peak = PEAK_SLOTS / 1e12
+    traffic, traffic_note = measured_traffic()
     out = {
         "metric": METRIC,
         "value": mixed["events_per_s"],
@@ -191,7 +296,8 @@ def main():
                    "events_per_iteration": EVENTS, "seed": 0, "precision": "fp32_mixed (f64 sums)",
                    "step": "one adaptation iteration: sample+map+integrand+sums+histograms+merge+stats+refine"},
         "roofline": {"bound": "alu", "kernel": "k_sample (event kernel)", "achieved": achieved,
-                     "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": None,
+                     "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "traffic_note": traffic_note,
                      "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
         "merge_kernel_ms": mixed["merge_kernel_ms"],
         "wall_ms_per_step": mixed["wall_ms_per_step"],
@@ -207,6 +313,10 @@ def main():
         out["c2_schedule"] = {"fp32_mixed": m, "fp64": f,
                               "mixed_minus_fp64_in_sigma": (m["integral"] - f["integral"]) / f["sigma"],
                               "exact": 0.99999999998770032}
+    if accum is not None:
+        out["accumulation_iteration"] = accum
+    if batch is not None:
+        out["batch256"] = batch
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]

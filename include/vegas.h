@@ -77,6 +77,7 @@ enum { VEGAS_FP64 = 0, VEGAS_FP32_MIXED = 1 };
 #define VEGAS_ITER_FULL 3u   /* a whole iteration in one call */
 #define VEGAS_NO_COMBINE 4u  /* (with CHUNK_END) record it but keep it out of the combination */
 #define VEGAS_REFINE 8u      /* (with CHUNK_END) refine the grid from this iteration's histograms */
+#define VEGAS_NO_HIST 16u    /* no histograms this iteration (every chunk of it); not with REFINE */
 
 typedef struct {
     int32_t dim;          /* d */
@@ -120,6 +121,11 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
  * chunks continue the event index (the first chunk starts at e = 0).
  * flags: VEGAS_ITER_FULL for a one-call iteration, or CHUNK_BEGIN, none, ...,
  * CHUNK_END over several calls; REFINE and NO_COMBINE act at CHUNK_END.
+ * VEGAS_NO_HIST skips the per-bin histograms (for an iteration on a frozen
+ * grid: the estimate is unchanged); it must be given on every chunk of the
+ * iteration or on none, never with REFINE, and the iteration's histogram row
+ * (vegas_last_iteration_device) then reads zero and vegas_refine has nothing
+ * to refine from.  EINVAL otherwise. 
  * At CHUNK_END: I_t = S1/M, var_t = (S2/M - I_t^2)/(M-1) over the M events
  * of the iteration (M >= 2), the iteration is recorded and t advances. */
 vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,

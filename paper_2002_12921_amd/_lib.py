@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "VEGAS_OK", -1: "VEGAS_EINVAL", -2: "VEGAS_ESTATE", -3: "VEGA
 
 GAUSS, BIMODAL, GENZ_DISC, GENZ_PEAK = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
-CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE = 1, 2, 3, 4, 8
+CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST = 1, 2, 3, 4, 8, 16
 
 # every symbol include/vegas.h declares
 EXPORTS = [

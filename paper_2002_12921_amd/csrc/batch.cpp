@@ -103,6 +103,7 @@ struct vegas_batch {
     std::vector<int64_t> events;
     int blocks = 0;
     size_t lds = 0;
+    int hrep_log2 = 0;
     uint64_t tile = 0;
     int n_items = 0;
     double tuned_ms = 0.0;
@@ -122,6 +123,7 @@ struct vegas_batch {
         a.queue = reinterpret_cast<uint32_t*>(at(L.queue));
         a.n_items = n_items;
         a.n_probs = n;
+        a.hrep_log2 = hrep_log2;
         return a;
     }
 };
@@ -176,8 +178,10 @@ vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s)
 {
     BatchArgs a = b->args();
     a.t = uint32_t(k);
-    VEGAS_HIP(launch_batch_sample(b->prec, b->kind, b->dmax, b->lds, a, b->blocks, s));
-    const int flags = k < b->n_adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : 0;
+    // accumulation iterations run on a frozen grid: no histograms
+    const bool adapt = k < b->n_adapt;
+    VEGAS_HIP(launch_batch_sample(b->prec, b->kind, b->dmax, b->lds, a, b->blocks, adapt, s));
+    const int flags = adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : MERGE_NO_HIST;
     VEGAS_HIP(launch_batch_finish(a, b->dmax, b->kind, k, flags, s));
     return VEGAS_OK;
 }
@@ -234,16 +238,19 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
     b->ws = dev_ws;
     b->L = L;
     int maxd = 0;
-    size_t lds = 0;
     for (int p = 0; p < n; ++p) {
         maxd = std::max(maxd, descs[p].dim);
-        lds = std::max(lds, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins));
         b->dims.push_back(descs[p].dim);
         b->bins.push_back(descs[p].n_bins);
         b->events.push_back(n_events[p]);
     }
     b->dmax = dmax_of(maxd);
-    b->lds = lds;
+    auto lds_for = [&](int rep) {
+        size_t m = 0;
+        for (int p = 0; p < n; ++p)
+            m = std::max(m, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, rep));
+        return m;
+    };
 
     hipError_t he;
     int dev = 0, cus = 0;
@@ -252,7 +259,20 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         (he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
         (he = hipStreamCreate(&b->priv)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "batch setup: %s", hipGetErrorString(he)));
-    b->blocks = std::max(1, cus * batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds));
+    // the most histogram replicas (16, 8, 4, 2) that keep the resident blocks
+    // per CU of a single copy; one copy otherwise
+    const int per_cu = batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds_for(1));
+    b->hrep_log2 = 0;
+    for (int l2 = 4; l2 >= 1; --l2) {
+        const size_t lds = lds_for(1 << l2);
+        if (lds + 256 > kLdsLimit) continue;
+        if (batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds) >= per_cu) {
+            b->hrep_log2 = l2;
+            break;
+        }
+    }
+    b->lds = lds_for(1 << b->hrep_log2);
+    b->blocks = std::max(1, cus * batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, b->lds));
     b->pinned_bytes = sizeof(DevResult) * n + 4096;
     if ((he = hipHostMalloc(&b->pinned, b->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
         b->pinned = nullptr;

@@ -93,6 +93,7 @@ struct vegas_ctx {
     int64_t t = 0;            // next iteration index
     int rec_idx = 0;          // recorded iterations
     bool in_chunk = false;
+    bool chunk_no_hist = false;  // the open iteration runs without histograms
     int64_t chunk_events = 0; // events already run in the open iteration
     bool has_hist = false;    // histograms of a finished iteration not yet refined from
     int blocks_user = 0;
@@ -251,7 +252,7 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     // as many histogram replicas (up to 16, one per bank pair) as the LDS
     // holds without losing a resident block
     for (int l2 = 4; l2 >= 1; --l2) {
-        if (lds_bytes(c->prec, c->kind, c->d, c->N, 1 << l2) + 256 > kLdsLimit) continue;
+        if (sample_lds(c->prec, c->kind, c->d, c->N, 1 << l2) > kLdsLimit) continue;
         if (sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, c->threads, 1 << l2) >= per_cu) {
             c->hrep_log2 = l2;
             break;
@@ -278,13 +279,17 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
 {
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40] (got %lld)", (long long)n);
-    if (flags & ~uint32_t(VEGAS_CHUNK_BEGIN | VEGAS_CHUNK_END | VEGAS_NO_COMBINE | VEGAS_REFINE))
+    if (flags & ~uint32_t(VEGAS_CHUNK_BEGIN | VEGAS_CHUNK_END | VEGAS_NO_COMBINE | VEGAS_REFINE | VEGAS_NO_HIST))
         return fail(VEGAS_EINVAL, "unknown flags 0x%x", flags);
     const bool begin = flags & VEGAS_CHUNK_BEGIN, end = flags & VEGAS_CHUNK_END;
+    const bool no_hist = flags & VEGAS_NO_HIST;
     if ((flags & (VEGAS_NO_COMBINE | VEGAS_REFINE)) && !end)
         return fail(VEGAS_EINVAL, "REFINE / NO_COMBINE only apply with CHUNK_END");
+    if (no_hist && (flags & VEGAS_REFINE)) return fail(VEGAS_EINVAL, "REFINE needs the histograms (NO_HIST given)");
     if (begin && c->in_chunk) return fail(VEGAS_ESTATE, "CHUNK_BEGIN while an iteration is open");
     if (!begin && !c->in_chunk) return fail(VEGAS_ESTATE, "no open iteration: start with CHUNK_BEGIN");
+    if (!begin && no_hist != c->chunk_no_hist)
+        return fail(VEGAS_EINVAL, "NO_HIST must be given on every chunk of an iteration or on none");
     const int64_t e0 = begin ? 0 : c->chunk_events;
     const int64_t M = e0 + n;
     if (M > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "iteration exceeds 2^40 events");
@@ -309,12 +314,13 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     a.N = c->N;
     a.pstride = c->L.pstride;
     a.hrep_log2 = c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2;
+    a.hist = no_hist ? 0 : 1;
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
     VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, c->threads, s));
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
     int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
-             ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0);
+             ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0) | (no_hist ? MERGE_NO_HIST : 0);
     VEGAS_HIP(launch_merge(merge_args(c, blocks, mf, double(M)), s));
     if (timed) {
         VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 2], s));
@@ -323,10 +329,11 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
 
     c->chunk_events = M;
     c->in_chunk = !end;
+    c->chunk_no_hist = no_hist;
     if (end) {
         c->t += 1;
         c->rec_idx += 1;
-        c->has_hist = !(flags & VEGAS_REFINE);
+        c->has_hist = !(flags & VEGAS_REFINE) && !no_hist;
         c->chunk_events = 0;
     }
     return VEGAS_OK;

@@ -50,11 +50,15 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // Precision policies and grid-table entry types.
 //
 // FP64: table entry (E_b, E_{b+1} - E_b); x = E_b + delta * width, u = x - centre.
-// FP32: table entry (RN32(E_b - centre_i), RN32(width) * 2^ws) -- the offset
-//   from the integrand's centre makes u = x - centre carry relative (not
-//   absolute) rounding error, and the power-of-two scaling keeps the width
-//   product near one; delta is pre-scaled by 2^-ws (exact).  The bimodal
-//   integrand has two centres: (E_b - cA, E_b - cB, scaled width, 0).
+// FP32: the map works on u' = (x - c) S with S = 2^(ws + 32).  With
+//   delta = (lo + h)/2^32 (see bin_words) and W = RN32(width), the table entry is
+//     (RN32((E_b - c + h W / 2^32) S), W 2^ws),
+//   so u' = RN32(lo) (W 2^ws) + first entry is one int-to-float convert and one
+//   FP32 fma: the convert rounds lo exactly as RN32(delta) would (delta itself
+//   is never formed), the offset from the integrand's centre c makes u carry
+//   rounding relative to u rather than to x, the factor 2^ws keeps the width
+//   product near one, and the integrand's constants absorb S^-1, S^-2 exactly.
+//   The bimodal integrand has two centres: (cA entry, cB entry, W 2^ws, 0).
 struct P64 {
     using real = double;
     static constexpr bool is64 = true;
@@ -85,8 +89,7 @@ __device__ __forceinline__ float exp2_unit(float z) { return __builtin_amdgcn_ex
 // where h = 1/2 for odd N and 0 for even N; since P + h never reaches the next
 // multiple of 2^32, the bin b = floor(yN) is the high word of P and
 // delta = yN - b = (lo + h) / 2^32, lo the low word.  The bin is exact in
-// every precision; FP64 gets delta exactly, FP32 gets RN32(delta) for even N
-// and delta within one FP32 ulp for odd N.
+// every precision and FP64 gets delta exactly; the FP32 map carries RN32(lo).
 struct BinConsts {
     uint32_t mul, add;  // N, floor(N/2)
     double h64;         // h / 2^32
@@ -105,16 +108,18 @@ template <class P, int KIND, int DMAX>
 struct EvalConsts {
     using real = typename P::real;
     real p1[DMAX], p2[DMAX];
-    double c64[DMAX];   // FP32 path, DISC: c_i (the exponent is summed in FP64)
-    real kexp, dscale;
-    double k2;          // FP32 path: log2(e)/a^2 (GAUSS, BIMODAL), log2(e) (DISC)
+    double c64[DMAX];   // FP32 path, DISC: c_i / S (the exponent is summed in FP64)
+    real kexp, dscale;  // dscale: FP32 path, 1/S = 2^-(ws + 32)
+    double k2;          // FP32 path: log2(e)/(a S)^2 (GAUSS, BIMODAL), log2(e) (DISC)
     BinConsts bc;
-    float dmul32, dadd32;  // FP32 path: delta * 2^-ws = fma(float(lo), dmul32, dadd32)
     double C, Cf, Cw;
 
     __device__ __forceinline__ void load(const DevConst* __restrict__ c)
     {
-        // only what the kernel's precision and integrand read (scalar registers are scarce)
+        // only what the kernel's precision and integrand read (scalar registers
+        // are scarce); the FP32 path works on u S, S = 2^(ws + 32), so its
+        // constants take the matching powers of 1/S (exact)
+        const double ds = double(c->dscale32) * 0x1p-32, ds2 = ds * ds;
 #pragma unroll
         for (int i = 0; i < DMAX; ++i) {
             p1[i] = real(0);
@@ -124,19 +129,17 @@ struct EvalConsts {
                 p1[i] = c->p1_64[i];
                 if constexpr (KIND != GAUSS) p2[i] = c->p2_64[i];
             } else {
-                if constexpr (KIND == GENZ_PEAK) p1[i] = c->p1_32[i];
-                if constexpr (KIND == GENZ_DISC) c64[i] = c->p1_64[i];
+                if constexpr (KIND == GENZ_PEAK) p1[i] = real(sqrt(c->p1_64[i]) * ds);  // c_i / S
+                if constexpr (KIND == GENZ_DISC) c64[i] = c->p1_64[i] * ds;
             }
         }
         kexp = P::is64 ? real(c->kexp64) : real(0);
-        k2 = c->kexp2_64;
-        dscale = real(c->dscale32);
+        k2 = (P::is64 || KIND == GENZ_DISC) ? c->kexp2_64 : c->kexp2_64 * ds2;
+        dscale = real(ds);
         const uint32_t N = uint32_t(c->n_bins);
         bc.mul = N;
         bc.add = N >> 1;
         bc.h64 = (N & 1u) ? 0x1p-33 : 0.0;
-        dmul32 = float(c->dscale32) * 0x1p-32f;
-        dadd32 = (N & 1u) ? float(c->dscale32) * 0x1p-33f : 0.0f;
         C = c->C;
         Cf = c->Cf;
         Cw = c->Cw;
@@ -154,12 +157,12 @@ struct EventEval {
     using tab_t = typename TabEntry<P, KIND>::type;
 
     int b[DMAX];      // bin of each dimension
-    real u[DMAX];     // x_i - centre_i (GAUSS, BIMODAL: mu / muA; DISC, PEAK: a_i)
-    real del[DMAX];   // position inside the bin (FP32: times 2^-ws)
+    real u[DMAX];     // x_i - centre_i (GAUSS, BIMODAL: mu / muA; DISC, PEAK: a_i); FP32: times S
+    real del[DMAX];   // FP64: position inside the bin; FP32: RN32(lo)
     real wp;          // width product (FP32: scaled, see ew)
     real F;           // integrand significand
     real s;           // GAUSS: sum u_i^2
-    double s64;       // GAUSS: sum u_i^2 as accumulated (FP64 in both paths)
+    double s64;       // GAUSS: sum u_i^2 as accumulated (FP64 in both paths; FP32: of u S)
     int ew;           // FP32: binary exponent taken out of the width product
     int fe;           // FP32: binary exponent of the integrand (f ~ 2^fe F)
 
@@ -198,12 +201,12 @@ struct EventEval {
                             if constexpr (KIND == BIMODAL) ubi = xi - c.p2[i];
                             if constexpr (KIND == GENZ_DISC || KIND == GENZ_PEAK) ui = xi - c.p2[i];
                         } else if constexpr (KIND == BIMODAL) {
-                            dl = fmaf(float(lo), c.dmul32, c.dadd32);
+                            dl = float(lo);
                             width = tb.z;
                             ui = fma(dl, tb.z, tb.x);
                             ubi = fma(dl, tb.z, tb.y);
                         } else {
-                            dl = fmaf(float(lo), c.dmul32, c.dadd32);
+                            dl = float(lo);
                             width = tb.y;
                             ui = fma(dl, tb.y, tb.x);
                         }
@@ -229,8 +232,13 @@ struct EventEval {
                                 sa = fma(c.p1[i], ui, sa);
                             else
                                 qa = fma(c.c64[i], double(ui), qa);
-                        } else {  // GENZ_PEAK: c^2 u^2 + 1
-                            den *= fma(c.p1[i] * ui, ui, real(1));
+                        } else {  // GENZ_PEAK: (c u)^2 + 1
+                            if constexpr (P::is64) {
+                                den *= fma(c.p1[i] * ui, ui, real(1));  // p1 = c^2
+                            } else {
+                                const real cu = c.p1[i] * ui;  // p1 = c / S, ui = u S
+                                den *= fma(cu, cu, real(1));
+                            }
                         }
                     }
                 }
@@ -285,8 +293,11 @@ struct EventEval {
         }
     }
 
+    // The product is rounded as written (no fusion into a following add), so
+    // every kernel variant accumulates the same rounded v.
     __device__ __forceinline__ double value(const EvalConsts<P, KIND, DMAX>& c) const
     {
+#pragma clang fp contract(off)
         if constexpr (P::is64)
             return F * wp * c.C;
         else
@@ -302,6 +313,10 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+
+// Event kernels add kGroup events per thread in plain FP64, then fold the
+// group's sums into Kahan-compensated S1, S2.
+constexpr int kGroup = 8;
 
 // Kahan step: s + (-c) tracks the running sum.
 __device__ __forceinline__ void kahan_add(double& s, double& c, double v)

@@ -29,20 +29,28 @@ __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2
 
 // Grid tables of dimension i from its edges E[0..N] (any address space).
 //   FP64: (E_b, E_{b+1} - E_b)
-//   FP32: (RN32(E_b - cA), [RN32(E_b - cB),] RN32(E_{b+1} - E_b) * 2^ws)
+//   FP32: with W = RN32(E_{b+1} - E_b), S = 2^(ws + 32) and g = E_b + h W / 2^32
+//         (h = 1/2 for odd N, else 0),
+//         (RN32((g - cA) S), [RN32((g - cB) S),] W 2^ws)
+//   The event kernel forms (x - c) S = RN32(lo) W 2^ws + first entry.
 __device__ static void write_tables(int i, const double* E, const DevConst* __restrict__ c, int kind,
                                     int N, double2* tab64, float* tab32)
 {
     const double cA = c->cA64[i], cB = c->cB64[i];
-    const float sc = 1.0f / c->dscale32;
+    const double sw = 1.0 / double(c->dscale32);  // 2^ws
+    const double S = sw * 0x1p32;
+    const double h = (N & 1) ? 0x1p-33 : 0.0;     // h / 2^32
     for (int b = threadIdx.x; b < N; b += blockDim.x) {
         const double lo = E[b], w = E[b + 1] - E[b];
         tab64[size_t(i) * N + b] = make_double2(lo, w);
+        const double W = double(float(w));
+        const double g = lo + h * W;
+        const float Ws = float(W * sw);
         if (kind == BIMODAL) {
             reinterpret_cast<float4*>(tab32)[size_t(i) * N + b] =
-                make_float4(float(lo - cA), float(lo - cB), float(w) * sc, 0.0f);
+                make_float4(float((g - cA) * S), float((g - cB) * S), Ws, 0.0f);
         } else {
-            reinterpret_cast<float2*>(tab32)[size_t(i) * N + b] = make_float2(float(lo - cA), float(w) * sc);
+            reinterpret_cast<float2*>(tab32)[size_t(i) * N + b] = make_float2(float((g - cA) * S), Ws);
         }
     }
 }
@@ -59,73 +67,81 @@ __device__ static double damp(double s, double alpha)
 // block (Lepage 1978 sec. 3, continuous rebinning): smooth with a 3-point
 // mean, normalise, damp, then put new edge k where the cumulative damped
 // weight, spread uniformly over each old bin, first reaches k/N of its total.
-// Wave 0 forms the sums and the cumulative weights C_b = r_0 + ... + r_b
-// (four bins per lane, then a scan across lanes; a running maximum keeps C
-// non-decreasing under rounding); every thread then places its new edges by
-// bisection on C.  Bins with r = 0 are never chosen: the first b with
-// C_b >= level has C_{b-1} < level <= C_b.
-__device__ static void refine_dim(const MergeArgs& a, int i, const double* h)
+// The smoothing and the damping (a log and a power in FP64) take one bin per
+// thread; wave 0 forms the two totals and the cumulative weights
+// C_b = r_0 + ... + r_b (four bins per lane, then a scan across lanes; a
+// running maximum keeps C non-decreasing under rounding); every thread then
+// places its new edges by bisection on C.  Bins with r = 0 are never chosen:
+// the first b with C_b >= level has C_{b-1} < level <= C_b.
+// Needs blockDim.x > N; Eo holds the current edges (LDS, filled by the
+// caller before a barrier).
+__device__ static void refine_dim(const MergeArgs& a, int i, const double* h, const double* Eo)
 {
     const int N = a.N;
-    __shared__ double Eo[kMaxBins + 1], En[kMaxBins + 1], Cs[kMaxBins + 1];
-    __shared__ int skip;
+    __shared__ double En[kMaxBins + 1], Cs[kMaxBins + 1];
+    __shared__ double tot[2];
     double* E = a.edges + size_t(i) * (N + 1);
-    for (int k = threadIdx.x; k <= N; k += blockDim.x) Eo[k] = E[k];
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double hv[4], sv[4];
-        double th = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int b = 4 * lane + q;
-            hv[q] = b < N ? h[b] : 0.0;
-            th += hv[q];
-            double sm = 0.0;
-            if (b < N) {
-                const double l = b > 0 ? h[b - 1] : 0.0;
-                const double rr = b < N - 1 ? h[b + 1] : 0.0;
-                if (b == 0)
-                    sm = (hv[q] + rr) / 2.0;
-                else if (b == N - 1)
-                    sm = (l + hv[q]) / 2.0;
-                else
-                    sm = (l + hv[q] + rr) / 3.0;
-            }
-            sv[q] = sm;
+    const int t = threadIdx.x;
+    if (t < N) {
+        const double l = t > 0 ? h[t - 1] : 0.0;
+        const double r = t < N - 1 ? h[t + 1] : 0.0;
+        double sm;
+        if (t == 0)
+            sm = (h[t] + r) / 2.0;
+        else if (t == N - 1)
+            sm = (l + h[t]) / 2.0;
+        else
+            sm = (l + h[t] + r) / 3.0;
+        Cs[t] = sm;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double th = 0.0, ts = 0.0;
+        for (int b = t; b < N; b += 64) {
+            th += h[b];
+            ts += Cs[b];
         }
-        const double tot = wave_sum(th);
-        if (lane == 0) skip = (tot == 0.0);
-        if (tot != 0.0) {
-            const double ssum = __shfl(wave_sum(sv[0] + sv[1] + sv[2] + sv[3]), 0, 64);
-            double c[4];
-            double run = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int b = 4 * lane + q;
-                run += b < N ? damp(sv[q] / ssum, a.alpha) : 0.0;
-                c[q] = run;
-            }
-            const double excl = wave_inclusive_scan(run) - run;
-            double mx = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                c[q] = fmax(excl + c[q], mx);
-                mx = c[q];
-            }
-            const double lane_max = wave_inclusive_max(mx);
-            const double prev = __shfl_up(lane_max, 1, 64);
-            const double floor_ = lane > 0 ? prev : 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int b = 4 * lane + q;
-                if (b < N) Cs[b] = fmax(c[q], floor_);
-            }
+        th = wave_sum(th);
+        ts = wave_sum(ts);
+        if (t == 0) {
+            tot[0] = th;
+            tot[1] = ts;
         }
     }
     __syncthreads();
-    if (skip) return;  // empty histogram: the grid and its tables stay
+    if (tot[0] == 0.0) return;  // empty histogram: the grid and its tables stay
+    if (t < N) Cs[t] = damp(Cs[t] / tot[1], a.alpha);
+    __syncthreads();
+    if (t < 64) {
+        const int lane = t;
+        double c[4];
+        double run = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * lane + q;
+            run += b < N ? Cs[b] : 0.0;
+            c[q] = run;
+        }
+        const double excl = wave_inclusive_scan(run) - run;
+        double mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = fmax(excl + c[q], mx);
+            mx = c[q];
+        }
+        const double lane_max = wave_inclusive_max(mx);
+        const double prev = __shfl_up(lane_max, 1, 64);
+        const double floor_ = lane > 0 ? prev : 0.0;
+        // each lane reads and writes only its own four bins
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * lane + q;
+            if (b < N) Cs[b] = fmax(c[q], floor_);
+        }
+    }
+    __syncthreads();
     const double R = Cs[N - 1];
-    for (int k = threadIdx.x; k <= N; k += blockDim.x) {
+    for (int k = t; k <= N; k += blockDim.x) {
         double e;
         if (k == 0 || k == N) {
             e = Eo[k];
@@ -158,23 +174,40 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
 {
     const int ncol = g == 0 ? 2 : a.N;
     const int off = g == 0 ? 0 : 2 + (g - 1) * a.N;
+    if (g > 0 && (a.flags & MERGE_NO_HIST)) {
+        // an iteration without histograms: its histogram row reads zero
+        if (a.flags & MERGE_END)
+            for (int k = threadIdx.x; k < ncol; k += blockDim.x) a.last[off + k] = 0.0;
+        return;
+    }
     int CW = 2;
     while (CW < ncol) CW <<= 1;          // columns per row pass (power of two)
     const int RL = kMergeThreads / CW;   // row lanes
     const int col = threadIdx.x % CW, rl = threadIdx.x / CW;
 
-    __shared__ double ps[kMergeThreads], pc[kMergeThreads], fin[kMaxBins + 1];
+    __shared__ double ps[kMergeThreads], pc[kMergeThreads], fin[kMaxBins + 1], Eo[kMaxBins + 1];
+    const bool refine = (a.flags & MERGE_END) && (a.flags & MERGE_REFINE) && g > 0;
+    // the edges the refinement needs, fetched while the rows are summed
+    if (refine && int(threadIdx.x) <= a.N) Eo[threadIdx.x] = a.edges[size_t(g - 1) * (a.N + 1) + threadIdx.x];
     double s = 0.0, c = 0.0;
     if (col < ncol) {
-        // rows rl, rl + RL, ...: loads issued eight at a time, then added in order
+        // rows rl, rl + RL, ...: loads issued sixteen at a time, then added in order
         const double* base = a.partials + off + col;
         int r = rl;
-        for (; r + 7 * RL < a.rows; r += 8 * RL) {
+        for (; r + 15 * RL < a.rows; r += 16 * RL) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = base[size_t(r + u * RL) * a.pstride];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) twosum_add(s, c, v[u]);
+        }
+        if (r + 7 * RL < a.rows) {
             double v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = base[size_t(r + u * RL) * a.pstride];
 #pragma unroll
             for (int u = 0; u < 8; ++u) twosum_add(s, c, v[u]);
+            r += 8 * RL;
         }
         for (; r < a.rows; r += RL) twosum_add(s, c, base[size_t(r) * a.pstride]);
     }
@@ -220,8 +253,8 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
     __syncthreads();
     if (g == 0) {
         if (threadIdx.x == 0) finish_iteration(a, fin[0], fin[1]);
-    } else if (a.flags & MERGE_REFINE) {
-        refine_dim(a, g - 1, fin);
+    } else if (refine) {
+        refine_dim(a, g - 1, fin, Eo);
     }
 }
 

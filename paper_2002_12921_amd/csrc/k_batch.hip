@@ -13,13 +13,16 @@
 
 namespace vegas {
 
-template <class P, int KIND, int DMAX>
+template <class P, int KIND, int DMAX, bool HIST>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_sample(BatchArgs a)
 {
     using tab_t = typename TabEntry<P, KIND>::type;
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(128) unsigned char smem[];
     __shared__ int s_item;
     __shared__ double red[kBlock / 64];
+    // histogram [dim][bin][replica], lane l adding into replica l mod rep
+    const int rl2 = a.hrep_log2, rep = 1 << rl2;
+    const int lrep = int(threadIdx.x) & (rep - 1);
     int cur = -1;
     int d = 0, N = 0, dN = 0;
     tab_t* tab = reinterpret_cast<tab_t*>(smem);
@@ -45,23 +48,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
             for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
-            hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15)));
+            hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
         }
-        for (int k = threadIdx.x; k < dN; k += kBlock) hist[k] = 0.0;
+        if constexpr (HIST)
+            for (int k = threadIdx.x; k < (dN << rl2); k += kBlock) hist[k] = 0.0;
         __syncthreads();
 
-        double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+        double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, g1 = 0.0, g2 = 0.0;
+        int ng = 0;
         for (uint64_t k = threadIdx.x; k < it.n; k += kBlock) {
             EventEval<P, KIND, DMAX> ev;
             ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
-            const double v = ev.value(cst);
-            const double v2 = v * v;
-            kahan_add(s1, c1, v);
-            kahan_add(s2, c2, v2);
+            double v, v2;
+            {
+                // rounded as written in every variant (with or without histograms)
+#pragma clang fp contract(off)
+                v = ev.value(cst);
+                v2 = v * v;
+                g1 += v;
+                g2 += v2;
+            }
+            if (++ng == kGroup) {
+                kahan_add(s1, c1, g1);
+                kahan_add(s2, c2, g2);
+                g1 = g2 = 0.0;
+                ng = 0;
+            }
+            if constexpr (HIST) {
 #pragma unroll
-            for (int i = 0; i < DMAX; ++i)
-                if (i < d) lds_atomic_add(&(hist + i * N)[ev.b[i]], v2);
+                for (int i = 0; i < DMAX; ++i)
+                    if (i < d) lds_atomic_add(&(hist + (i * N << rl2))[(ev.b[i] << rl2) | lrep], v2);
+            }
         }
+        kahan_add(s1, c1, g1);
+        kahan_add(s2, c2, g2);
+        // block_sum synchronises, which also completes every histogram atomic
         const double S1 = block_sum(s1 - c1, red);
         const double S2 = block_sum(s2 - c2, red);
         double* row = a.partials + it.row_off;
@@ -69,7 +90,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             row[0] = S1;
             row[1] = S2;
         }
-        for (int k = threadIdx.x; k < dN; k += kBlock) row[2 + k] = hist[k];
+        if constexpr (HIST) {
+            for (int k = threadIdx.x; k < dN; k += kBlock) {
+                double h = 0.0;
+                for (int r = 0; r < rep; ++r) h += hist[(k << rl2) + r];
+                row[2 + k] = h;
+            }
+        }
         __syncthreads();
     }
 }
@@ -158,45 +185,49 @@ hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind,
 
 // ---------------------------------------------------------------------------
 
-template <class P, int KIND>
+template <class P, int KIND, bool HIST>
 static const void* batch_fn(int dmax)
 {
     switch (dmax) {
-    case 4: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4>);
-    case 8: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8>);
-    case 16: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16>);
-    case 32: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 32>);
-    default: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 64>);
+    case 4: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4, HIST>);
+    case 8: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8, HIST>);
+    case 16: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16, HIST>);
+    case 32: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 32, HIST>);
+    default: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 64, HIST>);
     }
 }
 
-template <class P>
+template <class P, bool HIST>
 static const void* batch_fn_kind(int kind, int dmax)
 {
     switch (kind) {
-    case GAUSS: return batch_fn<P, GAUSS>(dmax);
-    case BIMODAL: return batch_fn<P, BIMODAL>(dmax);
-    case GENZ_DISC: return batch_fn<P, GENZ_DISC>(dmax);
-    default: return batch_fn<P, GENZ_PEAK>(dmax);
+    case GAUSS: return batch_fn<P, GAUSS, HIST>(dmax);
+    case BIMODAL: return batch_fn<P, BIMODAL, HIST>(dmax);
+    case GENZ_DISC: return batch_fn<P, GENZ_DISC, HIST>(dmax);
+    default: return batch_fn<P, GENZ_PEAK, HIST>(dmax);
     }
 }
 
-static const void* batch_kernel(int prec, int kind, int dmax)
+static const void* batch_kernel(int prec, int kind, int dmax, bool hist)
 {
-    return prec == FP64 ? batch_fn_kind<P64>(kind, dmax) : batch_fn_kind<P32>(kind, dmax);
+    if (hist) return prec == FP64 ? batch_fn_kind<P64, true>(kind, dmax) : batch_fn_kind<P32, true>(kind, dmax);
+    return prec == FP64 ? batch_fn_kind<P64, false>(kind, dmax) : batch_fn_kind<P32, false>(kind, dmax);
 }
 
+// Without histograms the launch keeps the same grid (and LDS size): it is a
+// work queue, so residency only sets how many blocks share the items.
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               hipStream_t s)
+                               bool hist, hipStream_t s)
 {
     void* args[] = {const_cast<BatchArgs*>(&a)};
-    return hipLaunchKernel(batch_kernel(prec, kind, dmax), dim3(blocks), dim3(kBlock), args, lds, s);
+    return hipLaunchKernel(batch_kernel(prec, kind, dmax, hist), dim3(blocks), dim3(kBlock), args, lds, s);
 }
 
 int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax), kBlock, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax, true), kBlock, lds) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

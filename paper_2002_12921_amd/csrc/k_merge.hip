@@ -20,11 +20,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(MergeArgs a)
 // Stand-alone refinement from the stored histograms of the last iteration.
 __global__ __launch_bounds__(kMergeThreads) void k_refine(MergeArgs a)
 {
-    __shared__ double h[kMaxBins];
+    __shared__ double h[kMaxBins], Eo[kMaxBins + 1];
     const int i = blockIdx.x;
     for (int b = threadIdx.x; b < a.N; b += blockDim.x) h[b] = a.last[2 + size_t(i) * a.N + b];
+    for (int b = threadIdx.x; b <= a.N; b += blockDim.x) Eo[b] = a.edges[size_t(i) * (a.N + 1) + b];
     __syncthreads();
-    refine_dim(a, i, h);
+    refine_dim(a, i, h, Eo);
 }
 
 // Derived constants of the integrand (see DevConst).

@@ -12,43 +12,89 @@
 
 namespace vegas {
 
-template <class P, int KIND, int DMAX, bool EXACT>
+// Histogram modes of the event kernel:
+//   kHistNone    no histograms (an iteration whose grid is not refined);
+//   kHistGeneral table first, then the histogram with runtime strides;
+//   kHistFixed   d in {4, 8}, N <= 64, 16 replicas: the histogram starts the
+//                LDS block with a compile-time stride of 64 bins x 16
+//                replicas (8 KiB) per dimension, so an atomic's address is
+//                one shift-add of the bin onto the lane's replica offset and
+//                the dimension's offset rides in the instruction's immediate
+//                field; the grid table follows the histogram.
+constexpr int kHistNone = 0, kHistGeneral = 1, kHistFixed = 2;
+constexpr int kFixBins = 64;
+constexpr int kFixRepLog2 = 4;
+constexpr int kFixDimBytes = kFixBins << (kFixRepLog2 + 3);
+
+template <class P, int KIND, int DMAX, bool EXACT, int HM>
 // aim for 8 waves per SIMD (two blocks per CU) without spilling; accept 4
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sample(SampleArgs a)
 {
+    constexpr bool FIX = HM == kHistFixed;
+    static_assert(!FIX || (EXACT && DMAX <= 8), "fixed layout: d <= 8 only");
     using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(128) unsigned char smem[];
     const int dN = a.d * a.N;
     const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127);
-    tab_t* tab = reinterpret_cast<tab_t*>(smem);
     // histogram [dim][bin][replica]: with 16 replicas every lane of a wave
     // adds into its own bank pair (lane mod 16), whatever its bin
-    const int rl2 = a.hrep_log2, rep = 1 << rl2;
+    const int rl2 = FIX ? kFixRepLog2 : a.hrep_log2, rep = 1 << rl2;
     const int lrep = int(threadIdx.x) & (rep - 1);
-    double* hist = reinterpret_cast<double*>(smem + tab_bytes);
-    double* red = hist + dN * rep;
+    const size_t hist_bytes = HM == kHistNone ? 0
+                              : FIX           ? size_t(DMAX) * kFixDimBytes
+                                              : size_t(dN) * rep * sizeof(double);
+    tab_t* tab = reinterpret_cast<tab_t*>(smem + (FIX ? hist_bytes : 0));
+    double* hist = reinterpret_cast<double*>(smem + (FIX ? 0 : tab_bytes));
+    double* red = reinterpret_cast<double*>(smem + tab_bytes + hist_bytes);
+    // the lane's replica within the bin: byte offset lrep * 8 (fixed layout)
+    unsigned char* hlane = smem + (lrep << 3);
 
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
     for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
-    for (int k = threadIdx.x; k < dN * rep; k += blockDim.x) hist[k] = 0.0;
+    for (int k = threadIdx.x; k < int(hist_bytes / sizeof(double)); k += blockDim.x) hist[k] = 0.0;
     __syncthreads();
 
     EvalConsts<P, KIND, DMAX> cst;
     cst.load(a.cst);
     const int d = EXACT ? DMAX : a.d;
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    double g1 = 0.0, g2 = 0.0;
+    int ng = 0;
+    // event k = j * stride + threadIdx.x * gridDim.x + blockIdx.x in pass j:
+    // the last, partial pass is spread over every block rather than a few
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < a.n; k += stride) {
+    for (uint64_t k = uint64_t(threadIdx.x) * gridDim.x + blockIdx.x; k < a.n; k += stride) {
         EventEval<P, KIND, DMAX, EXACT> ev;
         ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
-        const double v = ev.value(cst);
-        const double v2 = v * v;
-        kahan_add(s1, c1, v);
-        kahan_add(s2, c2, v2);
+        double v, v2;
+        {
+            // rounded as written in every variant (with or without histograms)
+#pragma clang fp contract(off)
+            v = ev.value(cst);
+            v2 = v * v;
+            g1 += v;
+            g2 += v2;
+        }
+        if (++ng == kGroup) {
+            kahan_add(s1, c1, g1);
+            kahan_add(s2, c2, g2);
+            g1 = g2 = 0.0;
+            ng = 0;
+        }
+        if constexpr (HM != kHistNone) {
 #pragma unroll
-        for (int i = 0; i < DMAX; ++i)
-            if (i < d) lds_atomic_add(&(hist + (i * a.N << rl2))[(ev.b[i] << rl2) | lrep], v2);
+            for (int i = 0; i < DMAX; ++i) {
+                if (i < d) {
+                    if constexpr (FIX)
+                        lds_atomic_add(reinterpret_cast<double*>(hlane + (i * kFixDimBytes + (ev.b[i] << (kFixRepLog2 + 3)))), v2);
+                    else
+                        lds_atomic_add(&(hist + (i * a.N << rl2))[(ev.b[i] << rl2) | lrep], v2);
+                }
+            }
+        }
     }
+    kahan_add(s1, c1, g1);
+    kahan_add(s2, c2, g2);
 
     // block_sum synchronises, which also completes every histogram atomic
     const double S1 = block_sum(s1 - c1, red);
@@ -58,10 +104,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         row[0] = S1;
         row[1] = S2;
     }
-    for (int k = threadIdx.x; k < dN; k += blockDim.x) {
-        double h = 0.0;
-        for (int r = 0; r < rep; ++r) h += hist[(k << rl2) + r];
-        row[2 + k] = h;
+    if constexpr (HM != kHistNone) {
+        for (int k = threadIdx.x; k < dN; k += blockDim.x) {
+            const int base = FIX ? ((k / a.N) * kFixBins + k % a.N) << rl2 : k << rl2;
+            double h = 0.0;
+            for (int r = 0; r < rep; ++r) h += hist[base + r];
+            row[2 + k] = h;
+        }
     }
 }
 
@@ -83,13 +132,15 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
         EventEval<P, KIND, DMAX> ev;
         ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
         double* row = a.out + k * size_t(3 * a.d + 2);
-        // x = centre + u, delta unscaled (exact), w and f with their exponents
+        // x = centre + u; delta as the kernel represents it (FP32: (RN32(lo) +
+        // h)/2^32, and u carries the factor S); w and f with their exponents
+        const double ds = P::is64 ? 1.0 : double(cst.dscale);
 #pragma unroll
         for (int i = 0; i < DMAX; ++i) {
             if (i < a.d) {
                 row[i] = double(ev.b[i]);
-                row[a.d + i] = P::is64 ? double(ev.del[i]) : double(ev.del[i] / cst.dscale);
-                row[2 * a.d + i] = double(ev.u[i]) + a.cst->cA64[i];
+                row[a.d + i] = P::is64 ? double(ev.del[i]) : double(ev.del[i]) * 0x1p-32 + cst.bc.h64;
+                row[2 * a.d + i] = double(ev.u[i]) * ds + a.cst->cA64[i];
             }
         }
         row[3 * a.d] = ldexp(double(ev.wp), ev.ew) * cst.Cw;
@@ -100,8 +151,8 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
 // Adjoint at fixed samples (Gaussian): per-thread FP64 sums of
 // v * d ln f / d theta_j, theta = (mu_0..mu_{d-1}, a):
 //   d ln f / d mu_j = 2 (x_j - mu_j) / a^2,  d ln f / d a = (2 s / a^2 - d) / a.
-// Block rows go to a partial table; the last block to finish merges the rows
-// in order and writes gout * sum / M.
+// Block rows go to a partial table; k_adjoint_merge adds them in order and
+// writes gout * sum / M.
 template <class P, int DMAX>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 {
@@ -119,9 +170,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     const DevConst* c = a.cst;
     EvalConsts<P, GAUSS, DMAX> cst;
     cst.load(c);
-    const real ka = P::is64 ? real(c->kexp64) : real(c->ka32);
+    // the FP32 path's u carries the factor S = 2^(ws + 32): its constants take S^-1, S^-2 (exact)
+    const double ds = P::is64 ? 1.0 : double(c->dscale32) * 0x1p-32;
+    const real ka = P::is64 ? real(c->kexp64) : real(double(c->ka32) * ds);
     const double inv_a = c->inv_a;
-    const double ka64 = c->kexp64;
+    const double ka64 = c->kexp64 * ds * ds;
     double g[DMAX + 1];
 #pragma unroll
     for (int j = 0; j <= DMAX; ++j) g[j] = 0.0;
@@ -192,29 +245,48 @@ static int dim_bucket(int d)
     default: { constexpr int D_ = 64; CALL; }  \
     }
 
-template <class P, int KIND>
-static const void* sample_fn(int d)
+// The histogram mode of a launch: none, or the fixed layout where it applies
+// (d in {4, 8}, N <= 64, 16 replicas), or the general one.
+static int hist_mode(int d, int N, int rep, bool hist)
 {
-    if (d == dim_bucket(d)) {
-        VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, true>))
+    if (!hist) return kHistNone;
+    return (d == 4 || d == 8) && N <= kFixBins && rep == (1 << kFixRepLog2) ? kHistFixed : kHistGeneral;
+}
+
+template <class P, int KIND>
+static const void* sample_fn(int d, int hm)
+{
+    if (hm == kHistFixed) {
+        if (d == 4) return reinterpret_cast<const void*>(&k_sample<P, KIND, 4, true, kHistFixed>);
+        return reinterpret_cast<const void*>(&k_sample<P, KIND, 8, true, kHistFixed>);
     }
-    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, false>))
+    if (hm == kHistNone) {
+        if (d == dim_bucket(d)) {
+            VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, true, kHistNone>))
+        }
+        VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, false, kHistNone>))
+    }
+    if (d == dim_bucket(d)) {
+        VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, true, kHistGeneral>))
+    }
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_sample<P, KIND, D_, false, kHistGeneral>))
 }
 
 template <class P>
-static const void* sample_fn_kind(int kind, int d)
+static const void* sample_fn_kind(int kind, int d, int hm)
 {
     switch (kind) {
-    case GAUSS: return sample_fn<P, GAUSS>(d);
-    case BIMODAL: return sample_fn<P, BIMODAL>(d);
-    case GENZ_DISC: return sample_fn<P, GENZ_DISC>(d);
-    default: return sample_fn<P, GENZ_PEAK>(d);
+    case GAUSS: return sample_fn<P, GAUSS>(d, hm);
+    case BIMODAL: return sample_fn<P, BIMODAL>(d, hm);
+    case GENZ_DISC: return sample_fn<P, GENZ_DISC>(d, hm);
+    default: return sample_fn<P, GENZ_PEAK>(d, hm);
     }
 }
 
-static const void* sample_kernel(int prec, int kind, int d)
+static const void* sample_kernel(int prec, int kind, int d, int N, int rep, bool hist)
 {
-    return prec == FP64 ? sample_fn_kind<P64>(kind, d) : sample_fn_kind<P32>(kind, d);
+    const int hm = hist_mode(d, N, rep, hist);
+    return prec == FP64 ? sample_fn_kind<P64>(kind, d, hm) : sample_fn_kind<P32>(kind, d, hm);
 }
 
 template <class P, int KIND>
@@ -240,17 +312,23 @@ static const void* adjoint_fn(int d)
     VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_>))
 }
 
-size_t sample_lds(int prec, int kind, int d, int N, int rep)
+size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist)
 {
-    return lds_bytes(prec, kind, d, N, rep) + sizeof(double) * (kBlock / 64);
+    const size_t red = sizeof(double) * (kBlock / 64);
+    switch (hist_mode(d, N, rep, hist)) {
+    case kHistNone: return lds_bytes(prec, kind, d, N, 0) + red;
+    case kHistFixed: return size_t(d) * kFixDimBytes + lds_bytes(prec, kind, d, N, 0) + red;
+    default: return lds_bytes(prec, kind, d, N, rep) + red;
+    }
 }
 
 hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, int threads, hipStream_t s)
 {
-    const void* fn = sample_kernel(prec, kind, a.d);
+    const int rep = 1 << a.hrep_log2;
+    const bool hist = a.hist != 0;
+    const void* fn = sample_kernel(prec, kind, a.d, a.N, rep, hist);
     void* args[] = {const_cast<SampleArgs*>(&a)};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
-                           sample_lds(prec, kind, a.d, a.N, 1 << a.hrep_log2), s);
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, sample_lds(prec, kind, a.d, a.N, rep, hist), s);
 }
 
 hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s)
@@ -279,8 +357,8 @@ hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_
 int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int rep)
 {
     int n = 0;
-    const void* fn = sample_kernel(prec, kind, d);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, sample_lds(prec, kind, d, N, rep)) != hipSuccess)
+    const void* fn = sample_kernel(prec, kind, d, N, rep, true);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, sample_lds(prec, kind, d, N, rep, true)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

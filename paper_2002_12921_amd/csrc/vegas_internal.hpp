@@ -160,6 +160,7 @@ struct SampleArgs {
     uint32_t key0, key1; // seed
     int d, N, pstride;
     int hrep_log2;       // log2 of the histogram replicas per bin
+    int hist;            // 0: no histograms this launch (only S1, S2 are written)
 };
 
 struct DumpArgs {
@@ -182,7 +183,7 @@ struct AdjointArgs {
     int d, N;
 };
 
-enum MergeFlags { MERGE_BEGIN = 1, MERGE_END = 2, MERGE_NO_COMBINE = 4, MERGE_REFINE = 8 };
+enum MergeFlags { MERGE_BEGIN = 1, MERGE_END = 2, MERGE_NO_COMBINE = 4, MERGE_REFINE = 8, MERGE_NO_HIST = 16 };
 
 struct MergeArgs {
     const double* partials;  // [rows][pstride]
@@ -241,13 +242,14 @@ struct BatchArgs {
     uint32_t* queue;    // next item to take (reset by the finish kernel)
     int n_items, n_probs;
     uint32_t t;         // iteration index
+    int hrep_log2;      // log2 of the histogram replicas per bin
 };
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).
 
 hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, int threads, hipStream_t s);
-size_t sample_lds(int prec, int kind, int d, int N, int rep);
+size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist = true);
 hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s);
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
@@ -265,7 +267,7 @@ hipError_t launch_copy_last(const DevResult* result, double* out2, hipStream_t s
 int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int rep);
 
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               hipStream_t s);
+                               bool hist, hipStream_t s);
 int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds);
 hipError_t launch_batch_finish(const BatchArgs& a, int dmax, int kind, int rec_idx, int flags, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind, hipStream_t s);

@@ -76,8 +76,9 @@ class Vegas:
 
     # -- the hot path ------------------------------------------------------
     def iterate(self, n_events: int, refine: bool = False, combine: bool = True,
-                chunk: Optional[str] = None):
-        """One iteration (or one chunk of one: chunk in {"begin", "mid", "end"})."""
+                chunk: Optional[str] = None, hist: bool = True):
+        """One iteration (or one chunk of one: chunk in {"begin", "mid", "end"}).
+        hist=False skips the histograms (a frozen grid; every chunk alike)."""
         flags = {None: _lib.ITER_FULL, "begin": _lib.CHUNK_BEGIN, "mid": 0,
                  "end": _lib.CHUNK_END, "begin_end": _lib.ITER_FULL}[chunk]
         if flags & _lib.CHUNK_END:
@@ -85,6 +86,8 @@ class Vegas:
                 flags |= _lib.REFINE
             if not combine:
                 flags |= _lib.NO_COMBINE
+        if not hist:
+            flags |= _lib.NO_HIST
         check(lib().vegas_iterate(self._ctx, int(n_events), flags, self._s()), "iterate")
 
     def refine(self):

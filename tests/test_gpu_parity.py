@@ -4,7 +4,7 @@ same points.
 Tolerances (FP64 path 1e-12 relative, FP32-mixed path 1e-6 relative, both
 before error propagation):
 * per-event records: bins exact; FP64 delta exact, x within 4 ulp, w and f to
-  rounding level; FP32 delta is exactly RN32 of the FP64 delta, x/w/f to FP32
+  rounding level; FP32 delta is RN32 of the FP64 delta (even N), x/w/f to FP32
   rounding level;
 * per-iteration sums S1, S2 relative; histograms per dimension normalised by
   that dimension's total (|dH| <= tol * sum_b H);
@@ -51,12 +51,21 @@ def _exponent(kind, params, x):
     return np.zeros(len(x))
 
 
-def _check_events(ev_gpu, ev_or, d, mixed, kind="gauss", params=None, N=50):
-    """Per-event bounds.  FP64: x to 4 ulp, w to 4d ulp, f to
+def _centres(kind, params, d):
+    """The per-dimension centre the FP32 table is offset from."""
+    if kind in ("gauss", "bimodal"):
+        return np.array(params[1:1 + d])
+    return np.array(params[d:2 * d])
+
+
+def _check_events(ev_gpu, ev_or, d, mixed, kind="gauss", params=None, N=50, E=None):
+    """Per-event bounds.  FP64: delta exact, x to 4 ulp, w to 4d ulp, f to
     eps (16 + 4 (8 + d) A) with A the integrand's exponent.  FP32: delta is
-    RN32 of the exact delta (even N; within one FP32 ulp for odd N), u = x -
-    centre carries ~3 ulp(u), so f carries 2^-24 (8 + 4d + (8 + d) A) and w
-    2^-24 (2d + 4)."""
+    (RN32(lo) + h)/2^32, i.e. RN32 of the exact delta for even N and within
+    one FP32 ulp of it for odd N; with w the bin's width and u = x - c the
+    offset from the table's centre, x carries at most 2^-24 (3 w + 2 |u|)
+    (the table's offset |u| + w, RN32(lo) w, RN32(w) w, the fma |u|); f
+    carries 2^-24 (8 + 4d + (8 + d) A) and w 2^-24 (2d + 4)."""
     b_g, b_o = ev_gpu[:, :d], ev_or[:, :d]
     assert np.array_equal(b_g, b_o), "bins differ"
     de_g, de_o = ev_gpu[:, d:2 * d], ev_or[:, d:2 * d]
@@ -76,7 +85,11 @@ def _check_events(ev_gpu, ev_or, d, mixed, kind="gauss", params=None, N=50):
             assert np.array_equal(de_g, de_o.astype(np.float32).astype(np.float64))
         else:
             assert np.all(np.abs(de_g - de_o) <= np.spacing(de_o.astype(np.float32)).astype(np.float64))
-        assert np.max(np.abs(x_g - x_o)) <= 4 * 2.0 ** -24
+        E = oracle.uniform_edges(d, N) if E is None else np.asarray(E)
+        bi = b_o.astype(np.int64)
+        width = np.stack([np.diff(E[i])[bi[:, i]] for i in range(d)], axis=1)
+        u = np.abs(x_o - _centres(kind, params, d)[None, :])
+        assert np.all(np.abs(x_g - x_o) <= 2.0 ** -24 * (3 * width + 2 * u) * 1.001 + 4 * EPS64)
         assert np.max(np.abs(w_g - w_o) / w_o) <= (2 * d + 4) * 2.0 ** -24
         assert np.all(rel <= 2.0 ** -24 * (8 + 4 * d + (8 + d) * A[big]))
 
@@ -91,7 +104,7 @@ def test_event_records(prec, d, N):
     t, first, count = 3, 1000, 4096 + 37
     got = v.dump_events(first, count, iteration=t).cpu().numpy()
     ref = oracle.events(oracle.Problem(d, N, oracle.GAUSS, params, seed=12345), E, t, first, count)
-    _check_events(got, ref, d, prec != "fp64", "gauss", params, N)
+    _check_events(got, ref, d, prec != "fp64", "gauss", params, N, E)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
@@ -120,6 +133,29 @@ def test_event_records_other_integrands(prec, kind, params_fn):
 def _hist_close(Hg, Ho, tol):
     tot = Ho.sum(axis=1, keepdims=True)
     return np.all(np.abs(Hg - Ho) <= tol * tot)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
+@pytest.mark.parametrize("d,N", [(4, 64), (8, 13), (8, 50), (8, 65), (5, 50)])
+def test_histogram_layouts(prec, tol, d, N):
+    """Sums and histograms with 16 replicas per bin (the fixed-stride layout
+    where d is 4 or 8 and N <= 64), with one copy, and with the automatic
+    choice, each against the oracle on the same adapted grid."""
+    params = _gauss(d, mu=0.37)
+    E = _adapted_edges(d, N, params)
+    M = 300_007
+    pr = oracle.Problem(d, N, oracle.GAUSS, params)
+    o1, o2, Ho = oracle.accumulate(pr, E, 0, M)
+    for rep in (16, 1, 0):
+        v = Vegas(d, N, "gauss", params, prec)
+        v.set_edges(E)
+        v.set_hist_replicas(rep)
+        v.iterate(M, combine=False)
+        S1, S2, H = v.last_iteration()
+        assert abs(S1 - o1) <= tol * abs(o1), (rep, S1, o1)
+        assert abs(S2 - o2) <= tol * abs(o2), (rep, S2, o2)
+        assert _hist_close(H, Ho, tol), rep
+        assert H.sum() > 0
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
@@ -410,3 +446,90 @@ def test_adjoint_c4_shape():
     v.adjoint(5, M, gout, grad)
     G, Gabs = oracle.adjoint(oracle.Problem(d, N, oracle.GAUSS, params), E, 5, M)
     assert np.all(np.abs(grad.cpu().numpy() - G / M) <= 1e-6 * Gabs / M)
+
+
+def _genz_params(kind, d):
+    if kind == "genz_disc":
+        return list(np.linspace(0.5, 1.5, d)) + list(np.linspace(0.05, 0.3, d))
+    return list(np.linspace(2.0, 4.0, d)) + list(np.linspace(0.3, 0.7, d))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
+@pytest.mark.parametrize("kind", ["genz_disc", "genz_peak"])
+def test_genz_d16_lockstep(kind, prec, tol):
+    """Genz discontinuous and product-peak integrands at d = 16 (both
+    normalised to 1): sums, histograms and refinements per iteration against
+    the oracle on the library's own grid.  The discontinuous one leaves whole
+    bins empty (x_i <= a_i contributes nothing), the refinement's r = 0 path."""
+    d, N, M = 16, 50, 60_001
+    params = _genz_params(kind, d)
+    kid = oracle.GENZ_DISC if kind == "genz_disc" else oracle.GENZ_PEAK
+    v = Vegas(d, N, kind, params, prec, seed=5)
+    pr = oracle.Problem(d, N, kid, params, seed=5)
+    for t in range(3):
+        E = v.edges()
+        v.iterate(M)
+        S1, S2, H = v.last_iteration()
+        o1, o2, Ho = oracle.accumulate(pr, E, t, M)
+        if kind == "genz_disc" and prec != "fp64":
+            # x_i > a_i is decided on the FP32 x: events within rounding of a
+            # threshold may flip, each moving at most max f w of the sums
+            tol = 1e-4
+        assert abs(S1 - o1) <= tol * abs(o1), (t, S1, o1)
+        assert abs(S2 - o2) <= tol * abs(o2), (t, S2, o2)
+        assert _hist_close(H, Ho, tol)
+        if kind == "genz_disc":
+            assert np.any(Ho == 0.0)  # empty bins below the thresholds
+        v.refine()
+        assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kind", ["genz_disc", "genz_peak"])
+def test_genz_d16_schedule_hits_closed_form(kind, prec):
+    """5 adaptation + 5 accumulation iterations of 1e6 events: the combined
+    estimate is within 5 sigma of the closed form (1 by normalisation)."""
+    d, N = 16, 50
+    v = Vegas(d, N, kind, _genz_params(kind, d), prec, seed=11)
+    for _ in range(5):
+        v.iterate(1_000_000, refine=True, combine=False)
+    for _ in range(5):
+        v.iterate(1_000_000)
+    r = v.result()
+    assert r["n_combined"] == 5
+    assert abs(r["integral"] - 1.0) <= 5 * r["sigma"], r
+    assert r["sigma"] < 0.02
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_no_hist_iterations(prec):
+    """Iterations without histograms (frozen grid) give bit-identical S1, S2
+    and combined results; their histogram row reads zero; they cannot refine."""
+    from paper_2002_12921_amd import VegasError
+    d, N, M = 8, 50, 400_009
+    params = _gauss(d)
+    a = Vegas(d, N, "gauss", params, prec)
+    b = Vegas(d, N, "gauss", params, prec)
+    for v in (a, b):
+        for _ in range(3):
+            v.iterate(M, refine=True, combine=False)
+    for _ in range(3):
+        a.iterate(M)
+        b.iterate(M, hist=False)
+        Sa, Sb = a.last_iteration(), b.last_iteration()
+        assert Sa[0] == Sb[0] and Sa[1] == Sb[1]
+        assert np.all(Sb[2] == 0.0) and Sa[2].sum() > 0
+    ra, rb = a.result(), b.result()
+    assert ra["integral"] == rb["integral"] and ra["sigma"] == rb["sigma"]
+    with pytest.raises(VegasError):
+        b.refine()  # nothing to refine from
+    with pytest.raises(VegasError):
+        b.iterate(M, refine=True, hist=False)
+    # chunks of one iteration must agree on NO_HIST
+    b.iterate(M // 2, chunk="begin", hist=False)
+    with pytest.raises(VegasError):
+        b.iterate(M // 2, chunk="end")
+    b.iterate(M - M // 2, chunk="end", hist=False)
+    a.iterate(M // 2, chunk="begin")
+    a.iterate(M - M // 2, chunk="end")
+    assert a.last_iteration()[0] == b.last_iteration()[0]
