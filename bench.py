@@ -112,8 +112,10 @@ def time_accumulation(precision: str, steps: int, warmup: int):
 def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0):
     """Two timed passes over `steps` adaptation iterations: the first with
     nothing but the HIP events around the whole region (the headline), the
-    second with the library's per-kernel events (event- and reduction-kernel
-    durations for the roofline)."""
+    second with the library's events around each kernel of each step, on the
+    stream the kernels run on (the event kernel's duration there sets the
+    roofline figure).  Then the event kernel alone, `steps` launches back to
+    back between two events, for comparison."""
     import torch
     from paper_2002_12921_amd import Vegas
 
@@ -142,11 +144,14 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
         v.iterate(EVENTS, refine=True, combine=False)
     sample_ms, merge_ms, n = v.timing_read()
     v.timing_enable(False)
+    # the event kernel alone: `steps` launches back to back between two events
+    b2b_ms = v.time_event_kernel(EVENTS, steps)
     return {
         "ms_per_step": total_ms / steps,
         "wall_ms_per_step": wall * 1e3 / steps,
         "events_per_s": _events_per_s(total_ms / steps),
         "event_kernel_ms": sample_ms / n,
+        "event_kernel_ms_back_to_back": b2b_ms,
         "merge_kernel_ms": merge_ms / n,
         "launch": v.launch_info(),
     }
@@ -299,13 +304,16 @@ def main():
                      "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_note": traffic_note,
                      "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
+        "event_kernel_ms_back_to_back": mixed["event_kernel_ms_back_to_back"],
         "merge_kernel_ms": mixed["merge_kernel_ms"],
         "wall_ms_per_step": mixed["wall_ms_per_step"],
         "launch": mixed["launch"],
     }
     if fp64 is not None:
         out["fp64"] = {"value": fp64["events_per_s"], "ms_per_step": fp64["ms_per_step"],
-                       "event_kernel_ms": fp64["event_kernel_ms"], "merge_kernel_ms": fp64["merge_kernel_ms"],
+                       "event_kernel_ms": fp64["event_kernel_ms"],
+                       "event_kernel_ms_back_to_back": fp64["event_kernel_ms_back_to_back"],
+                       "merge_kernel_ms": fp64["merge_kernel_ms"],
                        "launch": fp64["launch"]}
         out["mixed_over_fp64"] = mixed["events_per_s"] / fp64["events_per_s"]
     if sched:

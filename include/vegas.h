@@ -213,6 +213,15 @@ vegas_status vegas_get_launch(const vegas_ctx* ctx, int32_t* auto_blocks, int32_
 vegas_status vegas_timing_enable(vegas_ctx* ctx, int32_t enable);
 vegas_status vegas_timing_read(vegas_ctx* ctx, double* sample_ms, double* merge_ms, int64_t* count);
 
+/* Time the event kernel alone, for measurement: launch it reps times
+ * (1 <= reps <= 10000) back to back on the stream over n_events events of the
+ * current iteration t (with histograms unless no_hist), between two HIP events
+ * recorded on that stream, and set *ms to the elapsed time divided by reps.
+ * The partial rows it writes are scratch: nothing is recorded and t does not
+ * advance.  ESTATE while an iteration is open.  Synchronises. */
+vegas_status vegas_time_event_kernel(vegas_ctx* ctx, int64_t n_events, int32_t reps, int32_t no_hist,
+                                     double* ms, vegas_stream_t stream);
+
 /* Free the host context (the workspace stays the caller's). */
 vegas_status vegas_destroy(vegas_ctx* ctx);
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
     "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
     "vegas_get_iteration_index", "vegas_set_launch", "vegas_set_hist_replicas", "vegas_get_launch",
-    "vegas_timing_enable", "vegas_timing_read",
+    "vegas_timing_enable", "vegas_timing_read", "vegas_time_event_kernel",
     "vegas_destroy", "vegas_last_error",
     "vegas_batch_workspace_size", "vegas_batch_plan", "vegas_batch_run", "vegas_batch_results",
     "vegas_batch_get_edges", "vegas_batch_schedule", "vegas_batch_destroy",
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
         "vegas_set_hist_replicas": [vp, i32],
         "vegas_timing_enable": [vp, i32],
         "vegas_timing_read": [vp, pd, pd, P(i64)],
+        "vegas_time_event_kernel": [vp, i64, i32, i32, pd, vp],
         "vegas_destroy": [vp],
         "vegas_batch_workspace_size": [P(Desc), P(i64), i32, P(sz)],
         "vegas_batch_plan": [P(vp), P(Desc), P(i64), i32, vp, sz, i32, i32, vp],

@@ -144,6 +144,26 @@ int sample_blocks(const vegas_ctx* c, int64_t n)
     return nb;
 }
 
+SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
+{
+    SampleArgs a{};
+    a.cst = c->P.cst;
+    a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.partials = c->P.partials;
+    a.e0 = uint64_t(e0);
+    a.n = uint64_t(n);
+    a.t = uint32_t(c->t);
+    a.ctr3 = uint32_t(c->problem) << 8;
+    a.key0 = uint32_t(c->seed);
+    a.key1 = uint32_t(c->seed >> 32);
+    a.d = c->d;
+    a.N = c->N;
+    a.pstride = c->L.pstride;
+    a.hrep_log2 = c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2;
+    a.hist = no_hist ? 0 : 1;
+    return a;
+}
+
 MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
 {
     MergeArgs a{};
@@ -300,21 +320,7 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int blocks = sample_blocks(c, n);
-    SampleArgs a{};
-    a.cst = c->P.cst;
-    a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
-    a.partials = c->P.partials;
-    a.e0 = uint64_t(e0);
-    a.n = uint64_t(n);
-    a.t = uint32_t(c->t);
-    a.ctr3 = uint32_t(c->problem) << 8;
-    a.key0 = uint32_t(c->seed);
-    a.key1 = uint32_t(c->seed >> 32);
-    a.d = c->d;
-    a.N = c->N;
-    a.pstride = c->L.pstride;
-    a.hrep_log2 = c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2;
-    a.hist = no_hist ? 0 : 1;
+    const SampleArgs a = sample_args(c, e0, n, no_hist);
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
     VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, c->threads, s));
@@ -336,6 +342,32 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
         c->has_hist = !(flags & VEGAS_REFINE) && !no_hist;
         c->chunk_events = 0;
     }
+    return VEGAS_OK;
+}
+
+vegas_status vegas_time_event_kernel(vegas_ctx* c, int64_t n, int32_t reps, int32_t no_hist, double* ms,
+                                     vegas_stream_t stream)
+{
+    if (!c || !ms) return fail(VEGAS_EINVAL, "NULL argument");
+    if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40]");
+    if (reps < 1 || reps > 10000) return fail(VEGAS_EINVAL, "reps must be in [1, 10000]");
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int blocks = sample_blocks(c, n);
+    const SampleArgs a = sample_args(c, 0, n, no_hist != 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_sample(c->prec, c->kind, a, blocks, c->threads, s);
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float el = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&el, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(VEGAS_EHIP, "time_event_kernel: %s", hipGetErrorString(he));
+    *ms = double(el) / reps;
     return VEGAS_OK;
 }
 

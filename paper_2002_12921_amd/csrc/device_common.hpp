@@ -170,6 +170,9 @@ struct EventEval {
                                         uint64_t e, uint32_t t, uint32_t ctr3, uint32_t key0,
                                         uint32_t key1, int d_rt, int N)
     {
+        // every fused multiply-add here is an explicit fma(): nothing else is
+        // contracted, so all kernel variants round the same way
+#pragma clang fp contract(off)
         const int d = EXACT ? DMAX : d_rt;
         real w = real(1);
         real sa = real(0), sb = real(0);  // FP64 path: GAUSS/BIMODAL sums of squares; DISC: sum c u

@@ -33,26 +33,30 @@ __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2
 //         (h = 1/2 for odd N, else 0),
 //         (RN32((g - cA) S), [RN32((g - cB) S),] W 2^ws)
 //   The event kernel forms (x - c) S = RN32(lo) W 2^ws + first entry.
-__device__ static void write_tables(int i, const double* E, const DevConst* __restrict__ c, int kind,
-                                    int N, double2* tab64, float* tab32)
+__device__ __forceinline__ void write_table_entry(int i, int b, double lo, double hi, const DevConst* __restrict__ c,
+                                                  int kind, int N, double2* tab64, float* tab32)
 {
     const double cA = c->cA64[i], cB = c->cB64[i];
     const double sw = 1.0 / double(c->dscale32);  // 2^ws
     const double S = sw * 0x1p32;
     const double h = (N & 1) ? 0x1p-33 : 0.0;     // h / 2^32
-    for (int b = threadIdx.x; b < N; b += blockDim.x) {
-        const double lo = E[b], w = E[b + 1] - E[b];
-        tab64[size_t(i) * N + b] = make_double2(lo, w);
-        const double W = double(float(w));
-        const double g = lo + h * W;
-        const float Ws = float(W * sw);
-        if (kind == BIMODAL) {
-            reinterpret_cast<float4*>(tab32)[size_t(i) * N + b] =
-                make_float4(float((g - cA) * S), float((g - cB) * S), Ws, 0.0f);
-        } else {
-            reinterpret_cast<float2*>(tab32)[size_t(i) * N + b] = make_float2(float((g - cA) * S), Ws);
-        }
+    const double w = hi - lo;
+    tab64[size_t(i) * N + b] = make_double2(lo, w);
+    const double W = double(float(w));
+    const double g = lo + h * W;
+    const float Ws = float(W * sw);
+    if (kind == BIMODAL) {
+        reinterpret_cast<float4*>(tab32)[size_t(i) * N + b] =
+            make_float4(float((g - cA) * S), float((g - cB) * S), Ws, 0.0f);
+    } else {
+        reinterpret_cast<float2*>(tab32)[size_t(i) * N + b] = make_float2(float((g - cA) * S), Ws);
     }
+}
+
+__device__ static void write_tables(int i, const double* E, const DevConst* __restrict__ c, int kind,
+                                    int N, double2* tab64, float* tab32)
+{
+    for (int b = threadIdx.x; b < N; b += blockDim.x) write_table_entry(i, b, E[b], E[b + 1], c, kind, N, tab64, tab32);
 }
 
 // Damping of the refinement: r(s) = ((s - 1)/ln s)^alpha, r(0) = 0, r(1) = 1.
@@ -166,10 +170,82 @@ __device__ static void refine_dim(const MergeArgs& a, int i, const double* h, co
     write_tables(i, En, a.cst, a.kind, N, a.tab64, a.tab32);
 }
 
+// The same refinement for N <= 64 by one wave (lane b holds bin b's value hb
+// and the edges Eb = E_b, Eb1 = E_{b+1}), with no barrier: neighbours for the
+// smoothing, the totals, the cumulative weights and the searches all go
+// through cross-lane exchanges.  Each new interior edge k = lane is placed by
+// a branch-free lower-bound search (six probes) for the first bin whose C
+// reaches k R / N.  Called by a whole wave.
+__device__ static void refine_dim_wave(const MergeArgs& a, int i, double hb, double Eb, double Eb1)
+{
+    const int N = a.N, b = threadIdx.x & 63;
+    const bool in = b < N;
+    if (!in) hb = 0.0;
+    const double hl = __shfl_up(hb, 1, 64), hr = __shfl_down(hb, 1, 64);
+    double sm = 0.0;
+    if (in) {
+        if (b == 0)
+            sm = (hb + hr) / 2.0;
+        else if (b == N - 1)
+            sm = (hl + hb) / 2.0;
+        else
+            sm = (hl + hb + hr) / 3.0;
+    }
+    const double th = wave_sum(hb), ts = wave_sum(sm);
+    if (th == 0.0) return;  // empty histogram: the grid and its tables stay
+    const double r = in ? damp(sm / ts, a.alpha) : 0.0;
+    const double C = wave_inclusive_max(wave_inclusive_scan(r));  // non-decreasing under rounding
+    const double R = __shfl(C, N - 1, 64);
+    // new edge k = b (only 1 <= k <= N - 1 is used): lower bound of level in C
+    const double level = double(b) * R / double(N);
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int probe = pos + step - 1;
+        const double cp = __shfl(C, probe < 63 ? probe : 63, 64);
+        if (probe < N && cp < level) pos += step;
+    }
+    const double Am = __shfl(C, pos > 0 ? pos - 1 : 0, 64);
+    const double A = pos > 0 ? Am : 0.0;
+    const double Cp = __shfl(C, pos, 64);
+    const double Ep = __shfl(Eb, pos, 64), Ep1 = __shfl(Eb1, pos, 64);
+    const double e = Ep + (level - A) / (Cp - A) * (Ep1 - Ep);
+    double* E = a.edges + size_t(i) * (N + 1);
+    if (b >= 1 && b <= N - 1) E[b] = e;
+    // tables of bin b: lower edge (new edge b, or the fixed E_0), upper edge
+    // (new edge b + 1 from the next lane, or the fixed E_N)
+    const double up = __shfl_down(e, 1, 64);
+    if (in) {
+        const double lo = b == 0 ? Eb : e;
+        const double hi = b == N - 1 ? Eb1 : up;
+        write_table_entry(i, b, lo, hi, a.cst, a.kind, N, a.tab64, a.tab32);
+    }
+}
+
+// Stand-alone refinement of dimension i by the calling block from h (LDS):
+// one wave for N <= 64, the whole block otherwise.
+__device__ static void refine_any(const MergeArgs& a, int i, const double* h, const double* Eo)
+{
+    if (a.N <= 64) {
+        if (threadIdx.x < 64) {
+            const int b = threadIdx.x;
+            refine_dim_wave(a, i, b < a.N ? h[b] : 0.0, b <= a.N ? Eo[b] : 0.0, b < a.N ? Eo[b + 1] : 0.0);
+        }
+        return;
+    }
+    refine_dim(a, i, h, Eo);
+}
+
 // One column group of the reduction (group 0: S1, S2; group 1+i: the
-// histogram of dimension i): the partial rows are summed in order, folded
-// into the chunk accumulator (when there is one), and at the end of the
-// iteration the group records the statistics or refines its dimension.
+// histogram of dimension i): the partial rows are summed in a fixed order,
+// folded into the chunk accumulator (when there is one), and at the end of
+// the iteration the group records the statistics or refines its dimension.
+// Histogram groups: wave w adds rows w, w + 16, ... (lane = column, so each
+// load instruction reads consecutive columns of one row), 32 loads in
+// flight, with two-sums.  Group 0 spreads its rows over all lanes and folds
+// each wave with a butterfly.  After one barrier wave 0 adds the 16 wave
+// partials in order.  For N <= 64 wave 0 then refines with the column values
+// still in its registers.
 __device__ static void merge_group(const MergeArgs& a, const int g)
 {
     const int ncol = g == 0 ? 2 : a.N;
@@ -180,82 +256,112 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
             for (int k = threadIdx.x; k < ncol; k += blockDim.x) a.last[off + k] = 0.0;
         return;
     }
-    int CW = 2;
-    while (CW < ncol) CW <<= 1;          // columns per row pass (power of two)
-    const int RL = kMergeThreads / CW;   // row lanes
-    const int col = threadIdx.x % CW, rl = threadIdx.x / CW;
-
-    __shared__ double ps[kMergeThreads], pc[kMergeThreads], fin[kMaxBins + 1], Eo[kMaxBins + 1];
-    const bool refine = (a.flags & MERGE_END) && (a.flags & MERGE_REFINE) && g > 0;
+    constexpr int kWaves = kMergeThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double ws_s[kWaves][kMaxBins + 1], ws_c[kWaves][kMaxBins + 1];
+    __shared__ double fin[kMaxBins + 1], Eo[kMaxBins + 1];
+    const bool end = a.flags & MERGE_END;
+    const bool refine = end && (a.flags & MERGE_REFINE) && g > 0;
+    const bool wave_refine = refine && a.N <= 64;
     // the edges the refinement needs, fetched while the rows are summed
-    if (refine && int(threadIdx.x) <= a.N) Eo[threadIdx.x] = a.edges[size_t(g - 1) * (a.N + 1) + threadIdx.x];
-    double s = 0.0, c = 0.0;
-    if (col < ncol) {
-        // rows rl, rl + RL, ...: loads issued sixteen at a time, then added in order
-        const double* base = a.partials + off + col;
-        int r = rl;
-        for (; r + 15 * RL < a.rows; r += 16 * RL) {
-            double v[16];
+    double Eb = 0.0, Eb1 = 0.0;
+    if (wave_refine && wave == 0) {
+        const double* E = a.edges + size_t(g - 1) * (a.N + 1);
+        Eb = lane <= a.N ? E[lane] : 0.0;
+        Eb1 = lane < a.N ? E[lane + 1] : 0.0;
+    } else if (refine && !wave_refine && int(threadIdx.x) <= a.N) {
+        Eo[threadIdx.x] = a.edges[size_t(g - 1) * (a.N + 1) + threadIdx.x];
+    }
+    if (g == 0) {
+        // S1, S2: lane pairs take rows (thread t: row lane t / 2, column t % 2),
+        // then an exact two-sum butterfly over the pairs of the wave
+        const int col = lane & 1;
+        double s = 0.0, c = 0.0;
+        for (int r = int(threadIdx.x) >> 1; r < a.rows; r += kMergeThreads / 2)
+            twosum_add(s, c, a.partials[size_t(r) * a.pstride + col]);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = base[size_t(r + u * RL) * a.pstride];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) twosum_add(s, c, v[u]);
+        for (int o = 2; o < 64; o <<= 1) {
+            const double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
+            twosum_add(s, c, s2);
+            c += c2;
         }
-        if (r + 7 * RL < a.rows) {
+        if (lane < 2) {
+            ws_s[wave][col] = s;
+            ws_c[wave][col] = c;
+        }
+    }
+    for (int col = lane; g > 0 && col < ncol; col += 64) {
+        const double* base = a.partials + off + col;
+        double s = 0.0, c = 0.0;
+        int r = wave;
+        for (; r + 31 * kWaves < a.rows; r += 32 * kWaves) {
+            double v[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) v[u] = base[size_t(r + u * kWaves) * a.pstride];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) twosum_add(s, c, v[u]);
+        }
+        for (; r + 7 * kWaves < a.rows; r += 8 * kWaves) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = base[size_t(r + u * RL) * a.pstride];
+            for (int u = 0; u < 8; ++u) v[u] = base[size_t(r + u * kWaves) * a.pstride];
 #pragma unroll
             for (int u = 0; u < 8; ++u) twosum_add(s, c, v[u]);
-            r += 8 * RL;
         }
-        for (; r < a.rows; r += RL) twosum_add(s, c, base[size_t(r) * a.pstride]);
+        for (; r < a.rows; r += kWaves) twosum_add(s, c, base[size_t(r) * a.pstride]);
+        ws_s[wave][col] = s;
+        ws_c[wave][col] = c;
     }
-    ps[threadIdx.x] = s;
-    pc[threadIdx.x] = c;
     __syncthreads();
-    // combine the row lanes in a fixed order (tree over lanes)
-    for (int half = RL / 2; half > 0; half >>= 1) {
-        if (rl < half) {
-            const int o = threadIdx.x + half * CW;
-            double S = ps[threadIdx.x], C = pc[threadIdx.x];
-            twosum_add(S, C, ps[o]);
-            ps[threadIdx.x] = S;
-            pc[threadIdx.x] = C + pc[o];
+    if (wave != 0) {
+        if (!end || !refine || wave_refine) return;
+    } else {
+        double mine = 0.0;  // the value of column `lane` (first pass)
+        for (int col = lane; col < ncol; col += 64) {
+            double s = ws_s[0][col], c = ws_c[0][col];
+            for (int w = 1; w < kWaves; ++w) {
+                twosum_add(s, c, ws_s[w][col]);
+                c += ws_c[w][col];
+            }
+            const double val = s + c;
+            double hi, lo;
+            if (a.flags & MERGE_BEGIN) {
+                hi = val;
+                lo = 0.0;
+            } else {  // double-double accumulation across chunks
+                hi = a.acc[off + col];
+                lo = a.acc[a.pstride + off + col];
+                const double t = hi + val;
+                const double bp = t - hi;
+                lo += (hi - (t - bp)) + (val - bp);
+                hi = t;
+            }
+            if (a.acc) {
+                a.acc[off + col] = hi;
+                a.acc[a.pstride + off + col] = lo;
+            }
+            if (end) {
+                const double v = hi + lo;
+                a.last[off + col] = v;
+                fin[col] = v;
+                if (col == lane) mine = v;
+            }
         }
-        __syncthreads();
+        if (!end) return;
+        if (g == 0) {
+            const double S2 = __shfl(mine, 1, 64);
+            if (lane == 0) finish_iteration(a, mine, S2);
+            return;
+        }
+        if (wave_refine) {
+            refine_dim_wave(a, g - 1, mine, Eb, Eb1);
+            return;
+        }
+        if (!refine) return;
     }
-    if (rl == 0 && col < ncol) {
-        const double val = ps[col] + pc[col];
-        double hi, lo;
-        if (a.flags & MERGE_BEGIN) {
-            hi = val;
-            lo = 0.0;
-        } else {  // double-double accumulation across chunks
-            hi = a.acc[off + col];
-            lo = a.acc[a.pstride + off + col];
-            const double t = hi + val;
-            const double bp = t - hi;
-            lo += (hi - (t - bp)) + (val - bp);
-            hi = t;
-        }
-        if (a.acc) {
-            a.acc[off + col] = hi;
-            a.acc[a.pstride + off + col] = lo;
-        }
-        if (a.flags & MERGE_END) {
-            const double v = hi + lo;
-            a.last[off + col] = v;
-            fin[col] = v;
-        }
-    }
-    if (!(a.flags & MERGE_END)) return;
+    // N > 64: the whole block refines from fin (LDS)
     __syncthreads();
-    if (g == 0) {
-        if (threadIdx.x == 0) finish_iteration(a, fin[0], fin[1]);
-    } else if (refine) {
-        refine_dim(a, g - 1, fin, Eo);
-    }
+    refine_dim(a, g - 1, fin, Eo);
 }
 
 // Inverse-variance combination of the recorded iterations flagged for it

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_refine(MergeArgs a)
     for (int b = threadIdx.x; b < a.N; b += blockDim.x) h[b] = a.last[2 + size_t(i) * a.N + b];
     for (int b = threadIdx.x; b <= a.N; b += blockDim.x) Eo[b] = a.edges[size_t(i) * (a.N + 1) + b];
     __syncthreads();
-    refine_dim(a, i, h, Eo);
+    refine_any(a, i, h, Eo);
 }
 
 // Derived constants of the integrand (see DevConst).

@@ -168,6 +168,14 @@ class Vegas:
     def set_hist_replicas(self, replicas: int):
         check(lib().vegas_set_hist_replicas(self._ctx, replicas), "set_hist_replicas")
 
+    def time_event_kernel(self, n_events: int, reps: int, hist: bool = True) -> float:
+        """Milliseconds per launch of the event kernel alone (reps launches
+        back to back on the stream, between two HIP events)."""
+        ms = ctypes.c_double()
+        check(lib().vegas_time_event_kernel(self._ctx, int(n_events), int(reps), 0 if hist else 1,
+                                            ctypes.byref(ms), self._s()), "time_event_kernel")
+        return ms.value
+
     def timing_enable(self, enable: bool = True):
         check(lib().vegas_timing_enable(self._ctx, 1 if enable else 0), "timing_enable")
 

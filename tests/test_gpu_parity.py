@@ -533,3 +533,49 @@ def test_no_hist_iterations(prec):
     a.iterate(M // 2, chunk="begin")
     a.iterate(M - M // 2, chunk="end")
     assert a.last_iteration()[0] == b.last_iteration()[0]
+
+
+def test_time_event_kernel_leaves_state():
+    """The measurement entry point runs the event kernel only: the iteration
+    index, the records and the grid do not move."""
+    from paper_2002_12921_amd import VegasError
+    v = Vegas(8, 50, "gauss", _gauss(8), "fp32_mixed")
+    v.iterate(100_000, refine=True)
+    E, t = v.edges(), v.iteration_index
+    r0 = v.result()
+    ms = v.time_event_kernel(1_000_000, 3)
+    ms_nh = v.time_event_kernel(1_000_000, 3, hist=False)
+    assert ms > 0 and ms_nh > 0
+    assert v.iteration_index == t and np.array_equal(v.edges(), E)
+    r1 = v.result()
+    assert all(r1[k] == r0[k] or (r1[k] != r1[k] and r0[k] != r0[k]) for k in r0)  # NaN-aware
+    v.iterate(50_000, chunk="begin")
+    with pytest.raises(VegasError):
+        v.time_event_kernel(1000, 1)
+    v.iterate(50_000, chunk="end")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("d,N", [(3, 2), (3, 3), (4, 50), (2, 63), (2, 64), (2, 65), (2, 255)])
+def test_refine_matches_oracle_across_bin_counts(prec, d, N):
+    """Refinement (one wave for N <= 64, the whole block beyond) against the
+    oracle's refinement of the library's own histograms, fused at the end of
+    an iteration and stand-alone, plus the tables it rebuilds (checked through
+    the next iteration's sums)."""
+    params = _gauss(d, 0.2, 0.4)
+    E = _adapted_edges(d, N, params, iters=2, n=5000)
+    pr = oracle.Problem(d, N, oracle.GAUSS, params)
+    M = 40_000
+    for fused in (True, False):
+        v = Vegas(d, N, "gauss", params, prec)
+        v.set_edges(E)
+        v.iterate(M, refine=fused)
+        S1, S2, H = v.last_iteration()
+        if not fused:
+            v.refine()
+        En = v.edges()
+        assert np.max(np.abs(En - oracle.refine(H, E, 1.5))) <= 1e-12, (fused, N)
+        v.iterate(M)
+        o1, o2, _ = oracle.accumulate(pr, En, 1, M)
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert abs(v.last_iteration()[0] - o1) <= tol * abs(o1)
