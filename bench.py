@@ -112,10 +112,11 @@ def time_accumulation(precision: str, steps: int, warmup: int):
 def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0):
     """Two timed passes over `steps` adaptation iterations: the first with
     nothing but the HIP events around the whole region (the headline), the
-    second with the library's events around each kernel of each step, on the
-    stream the kernels run on (the event kernel's duration there sets the
-    roofline figure).  Then the event kernel alone, `steps` launches back to
-    back between two events, for comparison."""
+    second with the library's events around each kernel of each step (their
+    durations within a step; the event records themselves add a few
+    microseconds each).  Then the event kernel alone: `steps` launches back
+    to back between two events on its stream, whose duration per launch sets
+    the roofline figure."""
     import torch
     from paper_2002_12921_amd import Vegas
 
@@ -145,14 +146,14 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     sample_ms, merge_ms, n = v.timing_read()
     v.timing_enable(False)
     # the event kernel alone: `steps` launches back to back between two events
-    b2b_ms = v.time_event_kernel(EVENTS, steps)
+    kernel_ms = v.time_event_kernel(EVENTS, steps)
     return {
         "ms_per_step": total_ms / steps,
         "wall_ms_per_step": wall * 1e3 / steps,
         "events_per_s": _events_per_s(total_ms / steps),
-        "event_kernel_ms": sample_ms / n,
-        "event_kernel_ms_back_to_back": b2b_ms,
-        "merge_kernel_ms": merge_ms / n,
+        "event_kernel_ms": kernel_ms,
+        "event_kernel_ms_in_step": sample_ms / n,
+        "merge_kernel_ms_in_step": merge_ms / n,
         "launch": v.launch_info(),
     }
 
@@ -221,6 +222,32 @@ def batch_c5(reps: int):
             "finite_results": int(sum(1 for r in res if math.isfinite(r["integral"])))}
 
 
+def phase_split(steps: int):
+    """Event- and reduction-kernel times of three kinds of iteration on the
+    d = 8 workload (after 3 adaptation iterations): with refinement, without
+    refinement, and without histograms; per-kernel HIP events on the stream."""
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    out = {}
+    for prec in ("fp32_mixed", "fp64"):
+        v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, prec, seed=0, alpha=ALPHA)
+        for _ in range(3):
+            v.iterate(EVENTS, refine=True, combine=False)
+        torch.cuda.synchronize()
+        res = {}
+        for label, kw in (("refine", {"refine": True, "combine": False}), ("no_refine", {"combine": False}),
+                          ("no_hist", {"hist": False})):
+            v.timing_enable(True)
+            for _ in range(steps):
+                v.iterate(EVENTS, **kw)
+            s_ms, m_ms, n = v.timing_read()
+            v.timing_enable(False)
+            res[label] = {"event_kernel_ms": s_ms / n, "merge_kernel_ms": m_ms / n}
+        out[prec] = res
+    return out
+
+
 def cpu_baseline(iters: int):
     """The FP64 oracle (single-threaded C, as it stands) on the same workload:
     `iters` iterations of 1e7 events with refinement, seed 0."""
@@ -260,6 +287,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--phase-split", action="store_true",
+                    help="only time iterations with/without refinement and without histograms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path is "
@@ -271,6 +300,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe()
+    if args.phase_split:
+        print(json.dumps({"phase_split": phase_split(args.steps)}), flush=True)
+        return
 
     mixed = time_path("fp32_mixed", args.steps, args.warmup)
     fp64 = None if args.mixed_only else time_path("fp64", args.steps, args.warmup)
@@ -304,16 +336,16 @@ def main():
                      "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_note": traffic_note,
                      "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
-        "event_kernel_ms_back_to_back": mixed["event_kernel_ms_back_to_back"],
-        "merge_kernel_ms": mixed["merge_kernel_ms"],
+        "event_kernel_ms_in_step": mixed["event_kernel_ms_in_step"],
+        "merge_kernel_ms_in_step": mixed["merge_kernel_ms_in_step"],
         "wall_ms_per_step": mixed["wall_ms_per_step"],
         "launch": mixed["launch"],
     }
     if fp64 is not None:
         out["fp64"] = {"value": fp64["events_per_s"], "ms_per_step": fp64["ms_per_step"],
                        "event_kernel_ms": fp64["event_kernel_ms"],
-                       "event_kernel_ms_back_to_back": fp64["event_kernel_ms_back_to_back"],
-                       "merge_kernel_ms": fp64["merge_kernel_ms"],
+                       "event_kernel_ms_in_step": fp64["event_kernel_ms_in_step"],
+                       "merge_kernel_ms_in_step": fp64["merge_kernel_ms_in_step"],
                        "launch": fp64["launch"]}
         out["mixed_over_fp64"] = mixed["events_per_s"] / fp64["events_per_s"]
     if sched:
