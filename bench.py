@@ -222,6 +222,36 @@ def batch_c5(reps: int):
             "finite_results": int(sum(1 for r in res if math.isfinite(r["integral"])))}
 
 
+def c3_streamed():
+    """The d = 20 bimodal workload (a = 0.05 at 1/3 and 2/3, N = 100, FP32-mixed):
+    10 iterations of 1e8 events, each streamed as 10 chunks of 1e7 (5
+    adaptation iterations, then 5 accumulation iterations without histograms)."""
+    import torch
+    from paper_2002_12921_amd import Vegas, workloads
+
+    v = Vegas(20, 100, "bimodal", workloads.bimodal20(), "fp32_mixed", seed=0, alpha=ALPHA)
+    chunks, per = 10, 10_000_000
+
+    def iteration(adapt: bool):
+        for k in range(chunks):
+            ch = "begin" if k == 0 else ("end" if k == chunks - 1 else "mid")
+            v.iterate(per, chunk=ch, refine=adapt, combine=not adapt, hist=adapt)
+
+    iteration(True)  # warm-up (its own grid step)
+    v.reset_results()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for it in range(10):
+        iteration(it < 5)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    r = v.result()
+    return {"events_per_s": 10 * chunks * per / (ms * 1e-3), "ms_total": ms, "integral": r["integral"],
+            "sigma": r["sigma"], "chi2_dof": r["chi2_dof"], "exact": 1.0}
+
+
 def phase_split(steps: int):
     """Event- and reduction-kernel times of three kinds of iteration on the
     d = 8 workload (after 3 adaptation iterations): with refinement, without
@@ -308,6 +338,7 @@ def main():
     fp64 = None if args.mixed_only else time_path("fp64", args.steps, args.warmup)
     sched = {} if args.mixed_only else {p: c2_schedule(p) for p in ("fp32_mixed", "fp64")}
     batch = None if args.mixed_only or args.batch_reps <= 0 else batch_c5(args.batch_reps)
+    c3 = None if args.mixed_only else c3_streamed()
     accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
                                           for p in ("fp32_mixed", "fp64")}
 
@@ -357,6 +388,8 @@ def main():
         out["accumulation_iteration"] = accum
     if batch is not None:
         out["batch256"] = batch
+    if c3 is not None:
+        out["bimodal_d20_streamed"] = c3
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]

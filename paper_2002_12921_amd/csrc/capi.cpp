@@ -258,24 +258,28 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     if ((he = hipGetDevice(&c->device)) != hipSuccess ||
         (he = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "device query: %s", hipGetErrorString(he)));
-    // block size with the most resident waves per CU (ties: the larger block,
-    // which means fewer partial rows to reduce)
-    int best_waves = 0, per_cu = 1;
+    // Launch shape of the event kernel: block size and histogram replicas.
+    // Score = resident waves per CU x a replica factor x a block-size factor.
+    // The factors come from the d = 8 workload on gfx950: fewer replicas leave
+    // more LDS bank conflicts in the histogram atomics (4 replicas ran 17 %
+    // slower than 16 at equal occupancy), and 256-thread blocks pay more
+    // per-block set-up and partial rows than they gain (7 x 256 threads with
+    // 4 replicas ran 11 % slower than 3 x 512 with 8 in FP64).  Ties keep the
+    // larger block and the more replicas.
+    static const double kRepFactor[5] = {0.5, 0.65, 0.8, 0.93, 1.0};  // 1, 2, 4, 8, 16 replicas
+    double best = -1.0;
+    int per_cu = 1;
     for (int th : {1024, 512, 256}) {
-        const int bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1);
-        if (bpc * th / 64 > best_waves) {
-            best_waves = bpc * th / 64;
-            per_cu = bpc;
-            c->threads = th;
-        }
-    }
-    // as many histogram replicas (up to 16, one per bank pair) as the LDS
-    // holds without losing a resident block
-    for (int l2 = 4; l2 >= 1; --l2) {
-        if (sample_lds(c->prec, c->kind, c->d, c->N, 1 << l2) > kLdsLimit) continue;
-        if (sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, c->threads, 1 << l2) >= per_cu) {
-            c->hrep_log2 = l2;
-            break;
+        for (int l2 = 4; l2 >= 0; --l2) {
+            if (sample_lds(c->prec, c->kind, c->d, c->N, 1 << l2) > kLdsLimit) continue;
+            const int bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1 << l2);
+            const double score = double(bpc * th / 64) * kRepFactor[l2] * (th == 256 ? 0.92 : 1.0);
+            if (score > best + 1e-9) {
+                best = score;
+                per_cu = bpc;
+                c->threads = th;
+                c->hrep_log2 = l2;
+            }
         }
     }
     int nb = c->cu_count * per_cu;

@@ -2,6 +2,8 @@
 // binning, the piecewise-linear map, the integrands and block reductions.
 #pragma once
 
+#include <type_traits>
+
 #include "vegas_internal.hpp"
 
 namespace vegas {
@@ -108,7 +110,8 @@ template <class P, int KIND, int DMAX>
 struct EvalConsts {
     using real = typename P::real;
     real p1[DMAX], p2[DMAX];
-    double c64[DMAX];   // FP32 path, DISC: c_i / S (the exponent is summed in FP64)
+    double c64[DMAX];   // FP32 path, DISC: c_i / S (exponent summed in FP64, d > 8)
+    float c32[DMAX];    // FP32 path, DISC: RN32(c_i / S) (exponent summed in FP32, d <= 8)
     real kexp, dscale;  // dscale: FP32 path, 1/S = 2^-(ws + 32)
     double k2;          // FP32 path: log2(e)/(a S)^2 (GAUSS, BIMODAL), log2(e) (DISC)
     BinConsts bc;
@@ -125,12 +128,16 @@ struct EvalConsts {
             p1[i] = real(0);
             p2[i] = real(0);
             c64[i] = 0.0;
+            c32[i] = 0.0f;
             if constexpr (P::is64) {
                 p1[i] = c->p1_64[i];
                 if constexpr (KIND != GAUSS) p2[i] = c->p2_64[i];
             } else {
                 if constexpr (KIND == GENZ_PEAK) p1[i] = real(sqrt(c->p1_64[i]) * ds);  // c_i / S
-                if constexpr (KIND == GENZ_DISC) c64[i] = c->p1_64[i] * ds;
+                if constexpr (KIND == GENZ_DISC) {
+                    c64[i] = c->p1_64[i] * ds;
+                    c32[i] = float(c64[i]);
+                }
             }
         }
         kexp = P::is64 ? real(c->kexp64) : real(0);
@@ -174,9 +181,14 @@ struct EventEval {
         // contracted, so all kernel variants round the same way
 #pragma clang fp contract(off)
         const int d = EXACT ? DMAX : d_rt;
+        // the FP32 path sums the exponent in FP32 up to d = 8 (error <= d 2^-24
+        // of the exponent) and in FP64 beyond, where that grows past the
+        // method's tolerance
+        constexpr bool kQ32 = !P::is64 && DMAX <= 8;
+        using q_t = typename std::conditional<kQ32, float, double>::type;
         real w = real(1);
         real sa = real(0), sb = real(0);  // FP64 path: GAUSS/BIMODAL sums of squares; DISC: sum c u
-        double qa = 0.0, qb = 0.0;        // FP32 path: the same sums, accumulated in FP64
+        q_t qa = q_t(0), qb = q_t(0);     // FP32 path: the same sums
         real den = real(1);               // PEAK: product of denominators
         bool inside = true;               // DISC: all x_i > a_i
         int ewl = 0;                      // FP32: exponent taken out of w
@@ -219,20 +231,22 @@ struct EventEval {
                         if constexpr (KIND == GAUSS) {
                             if constexpr (P::is64)
                                 sa = fma(ui, ui, sa);
-                            else  // u^2 of an FP32 u is exact in FP64
-                                qa = fma(double(ui), double(ui), qa);
+                            else  // (u^2 of an FP32 u is exact in FP64)
+                                qa = fma(q_t(ui), q_t(ui), qa);
                         } else if constexpr (KIND == BIMODAL) {
                             if constexpr (P::is64) {
                                 sa = fma(ui, ui, sa);
                                 sb = fma(ubi, ubi, sb);
                             } else {
-                                qa = fma(double(ui), double(ui), qa);
-                                qb = fma(double(ubi), double(ubi), qb);
+                                qa = fma(q_t(ui), q_t(ui), qa);
+                                qb = fma(q_t(ubi), q_t(ubi), qb);
                             }
                         } else if constexpr (KIND == GENZ_DISC) {
                             inside = inside && (ui > real(0));
                             if constexpr (P::is64)
                                 sa = fma(c.p1[i], ui, sa);
+                            else if constexpr (kQ32)
+                                qa = fma(c.c32[i], ui, qa);
                             else
                                 qa = fma(c.c64[i], double(ui), qa);
                         } else {  // GENZ_PEAK: (c u)^2 + 1
@@ -257,7 +271,7 @@ struct EventEval {
         }
         wp = w;
         s = sa;
-        s64 = P::is64 ? double(sa) : qa;
+        s64 = P::is64 ? double(sa) : double(qa);
         ew = ewl;
         if constexpr (P::is64) {
             fe = 0;
@@ -270,22 +284,22 @@ struct EventEval {
             else
                 F = real(1) / den;
         } else {
-            // FP32 significand, FP64 exponent: with the exponent A (base 2) summed
-            // in FP64, m = floor(A) and F = 2^(m - A) in (1/2, 1] in FP32, so
-            // f = 2^-m F Cf keeps FP64 range
+            // FP32 significand, FP64 exponent: with the exponent A (base 2)
+            // formed in FP64, m = floor(A) and F = 2^(m - A) in (1/2, 1] in
+            // FP32, so f = 2^-m F Cf keeps FP64 range
             s = float(qa);
             if constexpr (KIND == GAUSS) {
-                const double arg = qa * c.k2;
+                const double arg = double(qa) * c.k2;
                 const double m = floor(arg);
                 F = exp2_unit(float(m - arg));
                 fe = -int(m);
             } else if constexpr (KIND == BIMODAL) {
-                const double aa = qa * c.k2, ab = qb * c.k2;
+                const double aa = double(qa) * c.k2, ab = double(qb) * c.k2;
                 const double m = floor(fmin(aa, ab));
                 F = exp2_unit(float(fmax(m - aa, -200.0))) + exp2_unit(float(fmax(m - ab, -200.0)));
                 fe = -int(m);
             } else if constexpr (KIND == GENZ_DISC) {
-                const double arg = -qa * c.k2;  // qa = sum c (x - a) >= 0 inside
+                const double arg = -double(qa) * c.k2;  // qa = sum c (x - a) >= 0 inside
                 const double m = floor(arg);
                 F = inside ? exp2_unit(float(m - arg)) : 0.0f;
                 fe = -int(m);

@@ -51,7 +51,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
     for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
-    for (int k = threadIdx.x; k < int(hist_bytes / sizeof(double)); k += blockDim.x) hist[k] = 0.0;
+    {   // clear the histogram, 16 bytes per store (hist is 128-byte aligned), then an odd last double
+        double2* h2 = reinterpret_cast<double2*>(hist);
+        for (int k = threadIdx.x; k < int(hist_bytes / sizeof(double2)); k += blockDim.x)
+            h2[k] = make_double2(0.0, 0.0);
+        if ((hist_bytes & 8) && threadIdx.x == 0) hist[hist_bytes / sizeof(double) - 1] = 0.0;
+    }
     __syncthreads();
 
     EvalConsts<P, KIND, DMAX> cst;
@@ -104,9 +109,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         row[0] = S1;
         row[1] = S2;
     }
-    if constexpr (HM != kHistNone) {
+    if constexpr (FIX) {
+        // slot (i, b) of the fixed layout, 16 replicas read 2 at a time
+        for (int k = threadIdx.x; k < DMAX * kFixBins; k += blockDim.x) {
+            const int i = k / kFixBins, bb = k % kFixBins;
+            if (bb < a.N) {
+                const double2* h2 = reinterpret_cast<const double2*>(hist + (k << kFixRepLog2));
+                double h = 0.0;
+#pragma unroll
+                for (int r = 0; r < (1 << kFixRepLog2) / 2; ++r) {
+                    const double2 p = h2[r];
+                    h += p.x;
+                    h += p.y;
+                }
+                row[2 + i * a.N + bb] = h;
+            }
+        }
+    } else if constexpr (HM != kHistNone) {
         for (int k = threadIdx.x; k < dN; k += blockDim.x) {
-            const int base = FIX ? ((k / a.N) * kFixBins + k % a.N) << rl2 : k << rl2;
+            const int base = k << rl2;
             double h = 0.0;
             for (int r = 0; r < rep; ++r) h += hist[base + r];
             row[2 + k] = h;

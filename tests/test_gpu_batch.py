@@ -63,10 +63,12 @@ def test_batch_mixed_matches_single_problem_path():
         for k in range(n_iter):
             v.iterate(q["n_events"], refine=k < n_adapt, combine=k >= n_adapt)
         r = v.result()
-        # same points and kernels; only reduction order differs (the grids
-        # then differ at rounding level, which the FP32 tables can expose)
-        assert abs(res[p]["integral"] - r["integral"]) <= 1e-10 * abs(r["integral"]), p
-        assert abs(res[p]["sigma"] - r["sigma"]) <= 1e-9 * r["sigma"], p
+        # same points; the batch kernel (compiled for the batch's largest d)
+        # sums the exponent in FP64 where the single-problem kernel for d <= 8
+        # sums it in FP32, and the reduction order differs: the paths agree to
+        # the FP32-mixed tolerance
+        assert abs(res[p]["integral"] - r["integral"]) <= 1e-6 * abs(r["integral"]), p
+        assert abs(res[p]["sigma"] - r["sigma"]) <= 1e-5 * r["sigma"], p
         ref = _oracle_run(q, n_iter, n_adapt)
         I, s, _ = ref["final"]
         assert abs(res[p]["integral"] - I) <= 0.1 * s, p

@@ -136,7 +136,7 @@ def _hist_close(Hg, Ho, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
-@pytest.mark.parametrize("d,N", [(4, 64), (8, 13), (8, 50), (8, 65), (5, 50)])
+@pytest.mark.parametrize("d,N", [(4, 64), (8, 13), (8, 50), (8, 65), (5, 50), (3, 7)])
 def test_histogram_layouts(prec, tol, d, N):
     """Sums and histograms with 16 replicas per bin (the fixed-stride layout
     where d is 4 or 8 and N <= 64), with one copy, and with the automatic
@@ -504,7 +504,9 @@ def test_genz_d16_schedule_hits_closed_form(kind, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
 def test_no_hist_iterations(prec):
     """Iterations without histograms (frozen grid) give bit-identical S1, S2
-    and combined results; their histogram row reads zero; they cannot refine."""
+    and combined results; their histogram row reads zero; they cannot refine.
+    (The histograms' LDS atomics add in no fixed order, so two refinements of
+    the same events agree only to rounding: b takes a's adapted grid.)"""
     from paper_2002_12921_amd import VegasError
     d, N, M = 8, 50, 400_009
     params = _gauss(d)
@@ -513,6 +515,7 @@ def test_no_hist_iterations(prec):
     for v in (a, b):
         for _ in range(3):
             v.iterate(M, refine=True, combine=False)
+    b.set_edges(a.edges())
     for _ in range(3):
         a.iterate(M)
         b.iterate(M, hist=False)
