@@ -60,11 +60,18 @@ __device__ static void write_tables(int i, const double* E, const DevConst* __re
 }
 
 // Damping of the refinement: r(s) = ((s - 1)/ln s)^alpha, r(0) = 0, r(1) = 1.
+// The usual exponents take a square root and a product instead of pow
+// (within two roundings of it).
 __device__ static double damp(double s, double alpha)
 {
     if (s == 0.0) return 0.0;
     if (s == 1.0) return 1.0;
-    return pow((s - 1.0) / log(s), alpha);
+    const double x = (s - 1.0) / log(s);
+    if (alpha == 1.5) return x * sqrt(x);
+    if (alpha == 1.0) return x;
+    if (alpha == 0.5) return sqrt(x);
+    if (alpha == 2.0) return x * x;
+    return pow(x, alpha);
 }
 
 // Refinement of dimension i from its histogram h[0..N-1] (LDS), by the whole

@@ -639,3 +639,19 @@ def test_adjoint_vs_finite_differences_and_closed_form():
     mean, se = reps.mean(axis=0), reps.std(axis=0, ddof=1) / np.sqrt(len(reps))
     assert np.all(np.abs(mean - exact) <= 5 * se + 1e-12), (mean, exact, se)
     assert abs(exact[0]) > 10 * se[0]  # the check has power on mu_0
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.7, 1.0, 1.5, 2.0])
+def test_refine_damping_exponents(alpha):
+    """Refinement with the damping exponents that take the square-root and
+    product paths (0.5, 1, 1.5, 2), the general power (0.7) and no damping
+    exponent at all (0: every nonzero bin weighs the same), against the
+    oracle's refinement of the library's histograms."""
+    d, N, M = 4, 50, 100_000
+    params = _gauss(d, 0.15, 0.45)
+    E = _adapted_edges(d, N, params, iters=2, n=5000)
+    v = Vegas(d, N, "gauss", params, "fp64", alpha=alpha)
+    v.set_edges(E)
+    v.iterate(M, refine=True)
+    H = v.last_iteration()[2]
+    assert np.max(np.abs(v.edges() - oracle.refine(H, E, alpha))) <= 1e-12
