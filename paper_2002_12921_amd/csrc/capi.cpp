@@ -150,6 +150,7 @@ SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
     a.cst = c->P.cst;
     a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
     a.partials = c->P.partials;
+    a.hslots = c->P.hslots;
     a.e0 = uint64_t(e0);
     a.n = uint64_t(n);
     a.t = uint32_t(c->t);
@@ -168,6 +169,7 @@ MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
 {
     MergeArgs a{};
     a.partials = c->P.partials;
+    a.hslots = c->P.hslots;
     a.acc = c->P.acc;
     a.last = c->P.last;
     a.edges = c->P.edges;
@@ -365,6 +367,8 @@ vegas_status vegas_time_event_kernel(vegas_ctx* c, int64_t n, int32_t reps, int3
     if (he == hipSuccess) he = hipEventRecord(e0, s);
     for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_sample(c->prec, c->kind, a, blocks, c->threads, s);
     if (he == hipSuccess) he = hipEventRecord(e1, s);
+    // the launches added into the histogram accumulators: clear them
+    if (he == hipSuccess) he = launch_zero(c->P.hslots, size_t(kHistSlots) * c->d * c->N, s);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     float el = 0.0f;
     if (he == hipSuccess) he = hipEventElapsedTime(&el, e0, e1);

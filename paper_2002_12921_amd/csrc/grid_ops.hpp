@@ -247,9 +247,10 @@ __device__ static void refine_any(const MergeArgs& a, int i, const double* h, co
 // histogram of dimension i): the partial rows are summed in a fixed order,
 // folded into the chunk accumulator (when there is one), and at the end of
 // the iteration the group records the statistics or refines its dimension.
-// Histogram groups: wave w adds rows w, w + 16, ... (lane = column, so each
-// load instruction reads consecutive columns of one row), 32 loads in
-// flight, with two-sums.  Group 0 spreads its rows over all lanes and folds
+// Histogram groups (when the rows carry H, as in batches): wave w adds rows
+// w, w + 16, ... (lane = column, so each load instruction reads consecutive
+// columns of one row), 32 loads in flight, with two-sums.  When the event
+// kernel accumulated H in slots instead, the group adds the slots.  Group 0 spreads its rows over all lanes and folds
 // each wave with a butterfly.  After one barrier wave 0 adds the 16 wave
 // partials in order.  For N <= 64 wave 0 then refines with the column values
 // still in its registers.
@@ -278,6 +279,38 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
         Eb1 = lane < a.N ? E[lane + 1] : 0.0;
     } else if (refine && !wave_refine && int(threadIdx.x) <= a.N) {
         Eo[threadIdx.x] = a.edges[size_t(g - 1) * (a.N + 1) + threadIdx.x];
+    }
+    if (g > 0 && a.hslots) {
+        // histogram accumulated by the event kernel in kHistSlots slots (over
+        // every chunk of the iteration): at its end, add the slots in order,
+        // clear them for the next iteration, record, refine
+        if (!end) return;
+        const size_t dN = size_t(a.d) * a.N;
+        double mine = 0.0;
+        for (int col = threadIdx.x; col < ncol; col += blockDim.x) {
+            double* h = a.hslots + size_t(g - 1) * a.N + col;
+            double v[kHistSlots];
+#pragma unroll
+            for (int q = 0; q < kHistSlots; ++q) v[q] = h[q * dN];
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < kHistSlots; ++q) {
+                sum += v[q];
+                h[q * dN] = 0.0;
+            }
+            a.last[off + col] = sum;
+            fin[col] = sum;
+            if (col == int(threadIdx.x)) mine = sum;
+        }
+        if (!refine) return;
+        if (wave_refine) {
+            // columns 0..N-1 are lanes 0..N-1 of wave 0
+            if (wave == 0) refine_dim_wave(a, g - 1, mine, Eb, Eb1);
+            return;
+        }
+        __syncthreads();
+        refine_dim(a, g - 1, fin, Eo);
+        return;
     }
     if (g == 0) {
         // S1, S2: lane pairs take rows (thread t: row lane t / 2, column t % 2),

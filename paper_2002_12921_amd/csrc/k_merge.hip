@@ -101,6 +101,7 @@ __global__ void k_init_state(ProblemPtrs p, int d, int N, int pstride)
     }
     for (int k = threadIdx.x; k < 2 * pstride; k += blockDim.x) p.acc[k] = 0.0;
     for (int k = threadIdx.x; k < pstride; k += blockDim.x) p.last[k] = 0.0;
+    for (int k = threadIdx.x; k < kHistSlots * (pstride - 2); k += blockDim.x) p.hslots[k] = 0.0;
     for (int k = threadIdx.x; k < 2 * kMaxRecords; k += blockDim.x) p.records[k] = 0.0;
     for (int k = threadIdx.x; k < kMaxRecords; k += blockDim.x) p.rec_flag[k] = 0;
     if (threadIdx.x == 0) {
@@ -109,6 +110,12 @@ __global__ void k_init_state(ProblemPtrs p, int d, int N, int pstride)
         R->integral = R->sigma = R->chi2_dof = R->last_integral = R->last_var = nan;
         R->n_iter = R->n_combined = R->n_events = R->n_nonfinite = 0;
     }
+}
+
+__global__ void k_zero(double* x, size_t n)
+{
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+        x[k] = 0.0;
 }
 
 __global__ void k_build_tables(ProblemPtrs p, int kind, int N)
@@ -171,6 +178,13 @@ hipError_t launch_prepare(int prec, int kind, int d, int N, const double* params
 hipError_t launch_init_state(const ProblemPtrs& p, int d, int N, int pstride, hipStream_t s)
 {
     hipLaunchKernelGGL(k_init_state, dim3(d + 1), dim3(256), 0, s, p, d, N, pstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* x, size_t n, hipStream_t s)
+{
+    const unsigned blocks = unsigned(n / 256 + 1 < 1024 ? n / 256 + 1 : 1024);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, x, n);
     return hipGetLastError();
 }
 

@@ -6,8 +6,10 @@
 // Layout: the grid's (lower edge, width) table [d][N] and the block's
 // histogram [d][N] (FP64) live in LDS; events never touch memory.  Each
 // thread strides over the launch's events; S1/S2 are Kahan-summed per thread,
-// reduced across the block, and each block writes one row
-// (S1, S2, H[d][N]) of the partial table with coalesced stores.
+// reduced across the block and written as the block's row (S1, S2) of the
+// partial table (summed later in a fixed order); the block's histogram is
+// added into one of kHistSlots accumulators with FP64 atomics (its sums come
+// from LDS atomics in no fixed order anyway).
 #include "device_common.hpp"
 
 namespace vegas {
@@ -109,8 +111,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         row[0] = S1;
         row[1] = S2;
     }
+    // the block's histogram (replicas summed) goes into slot blockIdx mod
+    // kHistSlots with device-scope FP64 atomics: no histogram row to write and
+    // read back, and 8 slots keep the atomics on one address few
+    double* slot = a.hslots + size_t(blockIdx.x % kHistSlots) * dN;
     if constexpr (FIX) {
-        // slot (i, b) of the fixed layout, 16 replicas read 2 at a time
+        // bin (i, b) of the fixed layout, 16 replicas read 2 at a time
         for (int k = threadIdx.x; k < DMAX * kFixBins; k += blockDim.x) {
             const int i = k / kFixBins, bb = k % kFixBins;
             if (bb < a.N) {
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                     h += p.x;
                     h += p.y;
                 }
-                row[2 + i * a.N + bb] = h;
+                atomicAdd(&slot[i * a.N + bb], h);
             }
         }
     } else if constexpr (HM != kHistNone) {
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const int base = k << rl2;
             double h = 0.0;
             for (int r = 0; r < rep; ++r) h += hist[base + r];
-            row[2 + k] = h;
+            atomicAdd(&slot[k], h);
         }
     }
 }

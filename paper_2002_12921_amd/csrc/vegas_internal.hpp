@@ -14,6 +14,9 @@ constexpr int kMaxParams = 1 + 2 * kMaxDim;
 constexpr int kMaxRecords = 1024;   // recorded iterations per context
 constexpr int kBlock = 1024;        // threads per block of the event kernels
 constexpr int kMaxBlocks = 2048;    // rows of the per-block partial table
+// The event kernel adds each block's histogram into slot (block mod
+// kHistSlots) with device-scope atomics; the reduction adds the slots.
+constexpr int kHistSlots = 8;
 constexpr int kMergeThreads = 1024; // threads per block of the reduction kernel
 constexpr size_t kLdsLimit = 160 * 1024;
 
@@ -62,6 +65,7 @@ struct Layout {
     size_t tab64;     // double2[d][N]  (E_b, E_{b+1}-E_b)
     size_t tab32;     // float2 or float4 [d][N]  (offsets from the centres, scaled width)
     size_t partials;  // double[kMaxBlocks][pstride]
+    size_t hslots;    // double[kHistSlots][d*N]  histogram accumulators of the event kernel
     size_t acc;       // double[2][pstride]   chunk accumulators (hi, lo)
     size_t last;      // double[pstride]      S1, S2, H of the last completed iteration
     size_t records;   // double[kMaxRecords][2]  (I_t, var_t)
@@ -86,6 +90,7 @@ inline Layout make_layout(int d, int N)
     L.tab64 = take(sizeof(double) * 2 * d * N);
     L.tab32 = take(sizeof(float) * 4 * d * N);
     L.partials = take(sizeof(double) * size_t(kMaxBlocks) * ps);
+    L.hslots = take(sizeof(double) * size_t(kHistSlots) * d * N);
     L.acc = take(sizeof(double) * 2 * size_t(ps));
     L.last = take(sizeof(double) * size_t(ps));
     L.records = take(sizeof(double) * 2 * kMaxRecords);
@@ -119,6 +124,7 @@ struct ProblemPtrs {
     double2* tab64;
     float* tab32;
     double* partials;
+    double* hslots;
     double* acc;
     double* last;
     double* records;
@@ -137,6 +143,7 @@ inline ProblemPtrs problem_ptrs(void* ws, const Layout& L)
     p.tab64 = reinterpret_cast<double2*>(b + L.tab64);
     p.tab32 = reinterpret_cast<float*>(b + L.tab32);
     p.partials = reinterpret_cast<double*>(b + L.partials);
+    p.hslots = reinterpret_cast<double*>(b + L.hslots);
     p.acc = reinterpret_cast<double*>(b + L.acc);
     p.last = reinterpret_cast<double*>(b + L.last);
     p.records = reinterpret_cast<double*>(b + L.records);
@@ -152,7 +159,8 @@ inline ProblemPtrs problem_ptrs(void* ws, const Layout& L)
 struct SampleArgs {
     const DevConst* cst;
     const void* tab;     // double2* (FP64) or float2* (FP32), [d][N]
-    double* partials;    // [gridDim.x][pstride]: S1, S2, H[d][N]
+    double* partials;    // [gridDim.x][pstride]: S1, S2 (the histogram goes to hslots)
+    double* hslots;      // [kHistSlots][d*N]: block b adds its histogram into slot b mod kHistSlots
     uint64_t e0;         // first event index of this launch
     uint64_t n;          // events in this launch
     uint32_t t;          // iteration index
@@ -187,6 +195,7 @@ enum MergeFlags { MERGE_BEGIN = 1, MERGE_END = 2, MERGE_NO_COMBINE = 4, MERGE_RE
 
 struct MergeArgs {
     const double* partials;  // [rows][pstride]
+    double* hslots;          // [kHistSlots][d*N] histogram accumulators, or null: the rows hold H
     double* acc;             // [2][pstride]
     double* last;            // [pstride]
     double* edges;           // [d][N+1]
@@ -258,6 +267,7 @@ hipError_t launch_prepare(int prec, int kind, int d, int N, const double* params
                           hipStream_t s);
 hipError_t launch_init_state(const ProblemPtrs& p, int d, int N, int pstride, hipStream_t s);
 hipError_t launch_build_tables(const ProblemPtrs& p, int kind, int d, int N, hipStream_t s);
+hipError_t launch_zero(double* x, size_t n, hipStream_t s);
 hipError_t launch_combine(const double* records, const int32_t* rec_flag, int n_rec, DevResult* result,
                           hipStream_t s);
 hipError_t launch_params_from(const void* src, int n, int is_fp32, double* dst, hipStream_t s);
