@@ -252,6 +252,70 @@ def c3_streamed():
             "sigma": r["sigma"], "chi2_dof": r["chi2_dof"], "exact": 1.0}
 
 
+def differentiable_c4(steps: int):
+    """The differentiable d = 8 case: centres mu ~ U[0.3, 0.7] (seed 0) and
+    a = 0.1 as FP32 parameters, FP32-mixed, a grid adapted by 5 iterations of
+    1e6 events; one forward + backward = an iteration of 1e7 events on the
+    frozen grid (VegasIntegral.forward) and the adjoint over the same points
+    (VegasIntegral.backward), through torch.autograd."""
+    import torch
+    from paper_2002_12921_amd import Vegas, workloads
+    from paper_2002_12921_amd.autograd import vegas_integral
+
+    mu0, a0 = workloads.c4_params()
+    params = [float(a0)] + [float(m) for m in mu0]
+    v = Vegas(D, NBINS, "gauss", params, "fp32_mixed", seed=0, alpha=ALPHA)
+    for _ in range(5):
+        v.iterate(1_000_000, refine=True, combine=False)
+    mu = torch.tensor(mu0, device="cuda", requires_grad=True)
+    a = torch.tensor(a0, device="cuda", requires_grad=True)
+
+    def step():
+        mu.grad = None
+        a.grad = None
+        vegas_integral(mu, a, v, EVENTS).backward()
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    return {"ms_per_forward_backward": ms, "events_per_s": EVENTS / (ms * 1e-3),
+            "grad_mu0": float(mu.grad[0]), "grad_a": float(a.grad)}
+
+
+def c1_small(reps: int):
+    """The d = 4 FP64 case: 10 iterations of 1e5 events, each refined after and
+    all combined, call by call (best of `reps` runs; at this size the launches,
+    not the events, set the time)."""
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    d, n_ev, n_iter = 4, 100_000, 10
+    params = [A] + [0.5] * d
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run():
+        v = Vegas(d, NBINS, "gauss", params, "fp64", seed=0, alpha=ALPHA)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(n_iter):
+            v.iterate(n_ev, refine=True)
+        stop.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop), v.result()
+
+    run()
+    ms, r = min((run() for _ in range(reps)), key=lambda x: x[0])
+    return {"ms_total": ms, "events_per_s": n_iter * n_ev / (ms * 1e-3), "integral": r["integral"],
+            "sigma": r["sigma"], "exact": 0.99999999999385016}
+
+
 def phase_split(steps: int):
     """Event- and reduction-kernel times of three kinds of iteration on the
     d = 8 workload (after 3 adaptation iterations): with refinement, without
@@ -339,6 +403,8 @@ def main():
     sched = {} if args.mixed_only else {p: c2_schedule(p) for p in ("fp32_mixed", "fp64")}
     batch = None if args.mixed_only or args.batch_reps <= 0 else batch_c5(args.batch_reps)
     c3 = None if args.mixed_only else c3_streamed()
+    c4 = None if args.mixed_only else differentiable_c4(args.steps)
+    c1 = None if args.mixed_only else c1_small(5)
     accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
                                           for p in ("fp32_mixed", "fp64")}
 
@@ -390,6 +456,10 @@ def main():
         out["batch256"] = batch
     if c3 is not None:
         out["bimodal_d20_streamed"] = c3
+    if c4 is not None:
+        out["differentiable_d8"] = c4
+    if c1 is not None:
+        out["gauss_d4_fp64_small"] = c1
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]

@@ -101,9 +101,17 @@ struct vegas_batch {
     std::vector<BatchProblem> probs;
     std::vector<int> dims, bins;
     std::vector<int64_t> events;
-    int blocks = 0;
-    size_t lds = 0;
-    int hrep_log2 = 0;
+    // one launch of the event kernel per dimension bucket present
+    struct Bucket {
+        int dmax = 0;
+        int lo = 0, hi = 0;  // item range (set with the schedule)
+        size_t lds = 0;
+        int blocks = 0;
+        int threads = kBlock;
+        int hrep_log2 = 0;
+    };
+    std::vector<Bucket> buckets;
+    int blocks = 0;  // the largest bucket launch (reported by vegas_batch_schedule)
     uint64_t tile = 0;
     int n_items = 0;
     double tuned_ms = 0.0;
@@ -121,9 +129,10 @@ struct vegas_batch {
         a.items = reinterpret_cast<const BatchItem*>(at(L.items));
         a.partials = reinterpret_cast<double*>(at(L.partials));
         a.queue = reinterpret_cast<uint32_t*>(at(L.queue));
-        a.n_items = n_items;
+        a.item_lo = 0;
+        a.item_hi = n_items;
         a.n_probs = n;
-        a.hrep_log2 = hrep_log2;
+        a.hrep_log2 = 0;
         return a;
     }
 };
@@ -156,6 +165,19 @@ void build_items(vegas_batch* b, uint64_t T, std::vector<BatchItem>& items)
         pr.n_items = int(items.size()) - pr.first_item;
     }
     b->n_items = int(items.size());
+    // dimensions run in decreasing order, so each bucket's items are contiguous
+    for (auto& bk : b->buckets) {
+        bk.lo = int(items.size());
+        bk.hi = 0;
+    }
+    for (int k = 0; k < int(items.size()); ++k) {
+        const int dm = dmax_of(b->dims[items[k].prob]);
+        for (auto& bk : b->buckets)
+            if (bk.dmax == dm) {
+                bk.lo = std::min(bk.lo, k);
+                bk.hi = std::max(bk.hi, k + 1);
+            }
+    }
 }
 
 vegas_status upload_schedule(vegas_batch* b, uint64_t T)
@@ -180,7 +202,15 @@ vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s)
     a.t = uint32_t(k);
     // accumulation iterations run on a frozen grid: no histograms
     const bool adapt = k < b->n_adapt;
-    VEGAS_HIP(launch_batch_sample(b->prec, b->kind, b->dmax, b->lds, a, b->blocks, adapt, s));
+    for (size_t q = 0; q < b->buckets.size(); ++q) {
+        const auto& bk = b->buckets[q];
+        BatchArgs ab = a;
+        ab.queue = a.queue + q;
+        ab.item_lo = bk.lo;
+        ab.item_hi = bk.hi;
+        ab.hrep_log2 = bk.hrep_log2;
+        VEGAS_HIP(launch_batch_sample(b->prec, b->kind, bk.dmax, bk.lds, ab, bk.blocks, bk.threads, adapt, s));
+    }
     const int flags = adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : MERGE_NO_HIST;
     VEGAS_HIP(launch_batch_finish(a, b->dmax, b->kind, k, flags, s));
     return VEGAS_OK;
@@ -245,13 +275,6 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         b->events.push_back(n_events[p]);
     }
     b->dmax = dmax_of(maxd);
-    auto lds_for = [&](int rep) {
-        size_t m = 0;
-        for (int p = 0; p < n; ++p)
-            m = std::max(m, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, rep));
-        return m;
-    };
-
     hipError_t he;
     int dev = 0, cus = 0;
     if ((he = hipStreamSynchronize(static_cast<hipStream_t>(stream))) != hipSuccess ||
@@ -259,20 +282,42 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         (he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
         (he = hipStreamCreate(&b->priv)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "batch setup: %s", hipGetErrorString(he)));
-    // the most histogram replicas (16, 8, 4, 2) that keep the resident blocks
-    // per CU of a single copy; one copy otherwise
-    const int per_cu = batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds_for(1));
-    b->hrep_log2 = 0;
-    for (int l2 = 4; l2 >= 1; --l2) {
-        const size_t lds = lds_for(1 << l2);
-        if (lds + 256 > kLdsLimit) continue;
-        if (batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, lds) >= per_cu) {
-            b->hrep_log2 = l2;
-            break;
+    // one event-kernel launch per dimension bucket present, each with the
+    // most histogram replicas (16, 8, 4, 2) that keep the resident blocks per
+    // CU of a single copy for that bucket's largest table and histogram
+    for (int dm : {64, 32, 16, 8, 4}) {
+        auto lds_for = [&](int rep) {
+            size_t m = 0;
+            for (int p = 0; p < n; ++p)
+                if (dmax_of(descs[p].dim) == dm)
+                    m = std::max(m, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, rep));
+            return m;
+        };
+        if (lds_for(1) == 0) continue;  // no problem in this bucket
+        vegas_batch::Bucket bk;
+        bk.dmax = dm;
+        // block size and replicas scored as for a single problem: resident
+        // waves x a replica factor (ties keep the larger block)
+        static const double kRepFactor[5] = {0.5, 0.65, 0.8, 0.93, 1.0};
+        double best = -1.0;
+        for (int th : {1024, 512}) {
+            for (int l2 = 4; l2 >= 0; --l2) {
+                const size_t lds = lds_for(1 << l2);
+                if (lds + 256 > kLdsLimit) continue;
+                const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th);
+                const double score = double(bpc * th / 64) * kRepFactor[l2];
+                if (score > best + 1e-9) {
+                    best = score;
+                    bk.threads = th;
+                    bk.hrep_log2 = l2;
+                    bk.lds = lds;
+                    bk.blocks = std::max(1, cus * bpc);
+                }
+            }
         }
+        b->blocks = std::max(b->blocks, bk.blocks);
+        b->buckets.push_back(bk);
     }
-    b->lds = lds_for(1 << b->hrep_log2);
-    b->blocks = std::max(1, cus * batch_max_blocks_per_cu(b->prec, b->kind, b->dmax, b->lds));
     b->pinned_bytes = sizeof(DevResult) * n + 4096;
     if ((he = hipHostMalloc(&b->pinned, b->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
         b->pinned = nullptr;

@@ -30,10 +30,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     EvalConsts<P, KIND, DMAX> cst;
     uint32_t key0 = 0, key1 = 0, ctr3 = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = int(atomicAdd(a.queue, 1u));
+        if (threadIdx.x == 0) s_item = a.item_lo + int(atomicAdd(a.queue, 1u));
         __syncthreads();
         const int item = s_item;
-        if (item >= a.n_items) break;  // every block leaves once the queue is empty
+        if (item >= a.item_hi) break;  // every block leaves once the queue is empty
         const BatchItem it = a.items[item];
         if (it.prob != cur) {
             cur = it.prob;
@@ -47,16 +47,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             cst.load(pr.cst);
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
-            for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
+            for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
             hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
         }
         if constexpr (HIST)
-            for (int k = threadIdx.x; k < (dN << rl2); k += kBlock) hist[k] = 0.0;
+            for (int k = threadIdx.x; k < (dN << rl2); k += blockDim.x) hist[k] = 0.0;
         __syncthreads();
 
         double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, g1 = 0.0, g2 = 0.0;
         int ng = 0;
-        for (uint64_t k = threadIdx.x; k < it.n; k += kBlock) {
+        for (uint64_t k = threadIdx.x; k < it.n; k += blockDim.x) {
             EventEval<P, KIND, DMAX> ev;
             ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
             double v, v2;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             row[1] = S2;
         }
         if constexpr (HIST) {
-            for (int k = threadIdx.x; k < dN; k += kBlock) {
+            for (int k = threadIdx.x; k < dN; k += blockDim.x) {
                 double h = 0.0;
                 for (int r = 0; r < rep; ++r) h += hist[(k << rl2) + r];
                 row[2 + k] = h;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 __global__ __launch_bounds__(kMergeThreads) void k_batch_finish(BatchArgs a, int kind, int rec_idx, int flags)
 {
     const int g = blockIdx.x, p = blockIdx.y;
-    if (p == 0 && g == 0 && threadIdx.x == 0) *a.queue = 0u;
+    if (p == 0 && g == 0 && threadIdx.x < kMaxBuckets) a.queue[threadIdx.x] = 0u;
     const BatchProblem pr = a.probs[p];
     if (g > pr.d) return;
     MergeArgs m{};
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_batch_finish(BatchArgs a, int
 __global__ __launch_bounds__(kMergeThreads) void k_batch_reset(BatchArgs a, int n_rec, int kind)
 {
     const int g = blockIdx.x, p = blockIdx.y;
-    if (p == 0 && g == 0 && threadIdx.x == 0) *a.queue = 0u;
+    if (p == 0 && g == 0 && threadIdx.x < kMaxBuckets) a.queue[threadIdx.x] = 0u;
     const BatchProblem pr = a.probs[p];
     if (g < pr.d) {
         double* E = pr.edges + size_t(g) * (pr.N + 1);
@@ -217,16 +217,16 @@ static const void* batch_kernel(int prec, int kind, int dmax, bool hist)
 // Without histograms the launch keeps the same grid (and LDS size): it is a
 // work queue, so residency only sets how many blocks share the items.
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               bool hist, hipStream_t s)
+                               int threads, bool hist, hipStream_t s)
 {
     void* args[] = {const_cast<BatchArgs*>(&a)};
-    return hipLaunchKernel(batch_kernel(prec, kind, dmax, hist), dim3(blocks), dim3(kBlock), args, lds, s);
+    return hipLaunchKernel(batch_kernel(prec, kind, dmax, hist), dim3(blocks), dim3(threads), args, lds, s);
 }
 
-int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds)
+int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax, true), kBlock, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax, true), threads, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;

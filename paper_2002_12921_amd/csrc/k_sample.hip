@@ -178,8 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
 // Adjoint at fixed samples (Gaussian): per-thread FP64 sums of
 // v * d ln f / d theta_j, theta = (mu_0..mu_{d-1}, a):
 //   d ln f / d mu_j = 2 (x_j - mu_j) / a^2,  d ln f / d a = (2 s / a^2 - d) / a.
-// Block rows go to a partial table; k_adjoint_merge adds them in order and
-// writes gout * sum / M.
+// Block rows go to a partial table; k_adjoint_merge adds them in a fixed
+// order and writes gout * sum / M.
 template <class P, int DMAX>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 {
@@ -232,14 +232,23 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     }
 }
 
-// Final step of the adjoint: block rows added in order (Neumaier), scaled by gout/M.
-__global__ __launch_bounds__(256) void k_adjoint_merge(AdjointArgs a, int rows)
+// Final step of the adjoint, scaled by gout/M: one wave per component j (and
+// j + 16, ...), lane l adding rows l, l + 64, ... in order with two-sums, then
+// an exact two-sum butterfly across the wave (the same pair on every lane).
+__global__ __launch_bounds__(kMergeThreads) void k_adjoint_merge(AdjointArgs a, int rows)
 {
     const double scale = *a.gout / double(a.n);
-    for (int j = threadIdx.x; j <= a.d; j += blockDim.x) {
-        double s = 0.0, cc = 0.0;
-        for (int r = 0; r < rows; ++r) neumaier_add(s, cc, a.partials[size_t(r) * (a.d + 1) + j]);
-        a.grad[j] = (s + cc) * scale;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j <= a.d; j += kMergeThreads / 64) {
+        double s = 0.0, c = 0.0;
+        for (int r = lane; r < rows; r += 64) twosum_add(s, c, a.partials[size_t(r) * (a.d + 1) + j]);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
+            twosum_add(s, c, s2);
+            c += c2;
+        }
+        if (lane == 0) a.grad[j] = (s + c) * scale;
     }
 }
 
@@ -377,7 +386,7 @@ hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_
     void* args[] = {const_cast<AdjointArgs*>(&a)};
     hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, lds, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adjoint_merge, dim3(1), dim3(256), 0, s, a, blocks);
+    hipLaunchKernelGGL(k_adjoint_merge, dim3(1), dim3(kMergeThreads), 0, s, a, blocks);
     return hipGetLastError();
 }
 

@@ -244,12 +244,17 @@ struct BatchItem {
     uint64_t row_off;
 };
 
+// Problems of a batch are grouped by dimension bucket (d <= 4, 8, 16, 32,
+// 64); each bucket's items are contiguous and run in a launch of their own.
+constexpr int kMaxBuckets = 5;
+
 struct BatchArgs {
     const BatchProblem* probs;
     const BatchItem* items;
     double* partials;
-    uint32_t* queue;    // next item to take (reset by the finish kernel)
-    int n_items, n_probs;
+    uint32_t* queue;    // this launch's work counter (the finish kernel re-arms all kMaxBuckets)
+    int item_lo, item_hi;  // this launch takes items [item_lo, item_hi)
+    int n_probs;
     uint32_t t;         // iteration index
     int hrep_log2;      // log2 of the histogram replicas per bin
 };
@@ -277,8 +282,8 @@ hipError_t launch_copy_last(const DevResult* result, double* out2, hipStream_t s
 int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int rep);
 
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               bool hist, hipStream_t s);
-int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds);
+                               int threads, bool hist, hipStream_t s);
+int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads);
 hipError_t launch_batch_finish(const BatchArgs& a, int dmax, int kind, int rec_idx, int flags, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind, hipStream_t s);
 hipError_t launch_batch_combine(const BatchArgs& a, int n_rec, hipStream_t s);
