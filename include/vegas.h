@@ -51,7 +51,8 @@ typedef enum {
     VEGAS_EWORKSPACE = -3,  /* workspace too small or misaligned */
     VEGAS_EHIP = -4,        /* a HIP runtime call failed (message kept) */
     VEGAS_ENONFINITE = -5,  /* a recorded iteration had a non-finite estimate */
-    VEGAS_EUNSUPPORTED = -6 /* valid request this build does not support */
+    VEGAS_EUNSUPPORTED = -6, /* valid request this build does not support */
+    VEGAS_ECOMPILE = -7      /* a user integrand's source did not compile (log kept) */
 } vegas_status;
 
 /* Integrands (sec. 3.1).  params layout (FP64, host pointer at init):
@@ -64,8 +65,11 @@ typedef enum {
  *                  params = c[0..d-1], a[0..d-1]                       (2d)
  *  VEGAS_GENZ_PEAK f = nu prod 1/(c_i^-2 + (x_i - a_i)^2)              (Eq. productpeak)
  *                  params = c[0..d-1], a[0..d-1]                       (2d)
- * For the Genz forms nu makes the integral over [0,1]^d one (sec. 3.1). */
-enum { VEGAS_GAUSS = 0, VEGAS_BIMODAL = 1, VEGAS_GENZ_DISC = 2, VEGAS_GENZ_PEAK = 3 };
+ * For the Genz forms nu makes the integral over [0,1]^d one (sec. 3.1).
+ *  VEGAS_USER      f given as device source code (see vegas_init_user); params
+ *                  is the caller's array of 0..129 values, handed to f as is;
+ *                  VEGAS_FP64 only. */
+enum { VEGAS_GAUSS = 0, VEGAS_BIMODAL = 1, VEGAS_GENZ_DISC = 2, VEGAS_GENZ_PEAK = 3, VEGAS_USER = 4 };
 
 /* Precision of the map and integrand.  Sums, histograms, statistics and the
  * grid are FP64 in both. */
@@ -112,6 +116,41 @@ vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes);
  * dimension.  The iteration index t starts at 0. */
 vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws,
                              size_t ws_bytes, vegas_stream_t stream);
+
+/* User integrands: the paper's route for integrands written in C, C++ or GPU
+ * code outside the framework (sec. 2.3), here as device source compiled at run
+ * time for gfx950 with hipRTC.  `source` is HIP device code that defines
+ *
+ *   __device__ double vegas_integrand(const double* x, int dim, const double* params);
+ *
+ * returning f(x) at the point x[0..dim-1] in [0,1)^dim; params points to the
+ * context's n_params FP64 values in device memory (vegas_desc.params, or
+ * those of vegas_set_params_device).  The macro VEGAS_DIM (= dim) is defined
+ * before the source, and the HIP device math library is available.  The
+ * source may define other __device__ functions and constants; it must not
+ * write memory it does not own, and the names vegas_user_* and namespace
+ * vegas are reserved.  Everything else of an iteration (points, map,
+ * Jacobian, sums, histograms, refinement, combination) is the library's FP64
+ * path, so a user integrand equal to a built-in one gives its results up to
+ * rounding.
+ *
+ * vegas_init_user: as vegas_init_grid for desc->integrand == VEGAS_USER and
+ * desc->precision == VEGAS_FP64 (else EINVAL / EUNSUPPORTED); 0 <= n_params <=
+ * 129 (params may be NULL when 0).  Compiles the source for desc->dim (about
+ * a second; code objects are kept per (dim, source) for the process) and
+ * loads it on the current device.  VEGAS_ECOMPILE if it does not compile,
+ * with the compiler's messages in vegas_last_error() (lines of the source are
+ * numbered from 1 in file "integrand").  Unsupported on a user context:
+ * vegas_adjoint (EUNSUPPORTED) and batches.  vegas_init_grid refuses
+ * VEGAS_USER (EINVAL). */
+vegas_status vegas_init_user(vegas_ctx** out, const vegas_desc* desc, const char* source, void* dev_ws,
+                             size_t ws_bytes, vegas_stream_t stream);
+
+/* Compile `source` for dimension dim (1..64) as vegas_init_user would, without
+ * a device: VEGAS_OK or VEGAS_ECOMPILE.  When log is not NULL the compiler's
+ * messages (warnings too) are copied there, NUL-terminated and cut to
+ * log_bytes. */
+vegas_status vegas_user_compile(const char* source, int32_t dim, char* log, size_t log_bytes);
 
 /* Run n_events events (1 <= n_events <= 2^40) of the current iteration t.
  * Event e draws, for each group j of four dimensions,

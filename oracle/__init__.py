@@ -12,6 +12,7 @@ method it follows, is documented in ``vegas_oracle.h``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -189,6 +190,38 @@ def events(pr: Problem, edges: np.ndarray, t: int, e0: int, n: int) -> np.ndarra
     out = np.zeros((n, 3 * pr.dim + 2))
     lib().vo_events(ctypes.byref(pr.c()), _dp(edges), t, e0, n, _dp(out))
     return out
+
+
+def accumulate_fn(dim: int, n_bins: int, seed: int, problem: int, edges: np.ndarray, t: int, n: int, f,
+                  e0: int = 0, with_abs: bool = False):
+    """(S1, S2, H[d, N]) of one iteration for an integrand given as a NumPy
+    function f(x) -> values, x of shape (n, d) in FP64 (a user integrand).
+
+    The points, bins and weights are the oracle's (``events``: Philox point,
+    bin and offset, the piecewise-linear map and its Jacobian w = prod N W_b,
+    none of which depends on the integrand, so the Gaussian integrand serves
+    only as a carrier); then v = f(x) w, S1 = sum v, S2 = sum v^2 and
+    H[i][b] = sum of v^2 over the events with b_i = b, the accumulators of the
+    per-event stage of the Vegas iteration (sec. 2.2), each sum rounded once
+    (math.fsum).  with_abs: also return sum |v| (the scale of S1's rounding
+    when f changes sign)."""
+    carrier = Problem(dim, n_bins, GAUSS, [0.1] + [0.5] * dim, seed=seed, problem=problem)
+    ev = events(carrier, edges, t, e0, n)
+    b = ev[:, :dim].astype(np.int64)
+    x = ev[:, 2 * dim:3 * dim]
+    w = ev[:, 3 * dim]
+    v = np.asarray(f(x), dtype=np.float64) * w
+    v2 = v * v
+    H = np.zeros((dim, n_bins))
+    for i in range(dim):
+        order = np.argsort(b[:, i], kind="stable")
+        bs, vs = b[order, i], v2[order]
+        cuts = np.searchsorted(bs, np.arange(n_bins + 1))
+        for k in range(n_bins):
+            H[i, k] = math.fsum(vs[cuts[k]:cuts[k + 1]])
+    if with_abs:
+        return math.fsum(v), math.fsum(v2), H, math.fsum(np.abs(v))
+    return math.fsum(v), math.fsum(v2), H
 
 
 def iteration_stats(S1: float, S2: float, M: float):

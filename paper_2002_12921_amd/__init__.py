@@ -9,4 +9,4 @@ Modules:
   build       hipcc build of the library
 """
 from ._lib import VegasError, lib  # noqa: F401
-from .integrator import Vegas  # noqa: F401
+from .integrator import Vegas, compile_user  # noqa: F401

@@ -12,17 +12,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvegas_gfx950.so")
 
 VEGAS_OK, VEGAS_EINVAL, VEGAS_ESTATE, VEGAS_EWORKSPACE = 0, -1, -2, -3
-VEGAS_EHIP, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED = -4, -5, -6
+VEGAS_EHIP, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED, VEGAS_ECOMPILE = -4, -5, -6, -7
 STATUS_NAMES = {0: "VEGAS_OK", -1: "VEGAS_EINVAL", -2: "VEGAS_ESTATE", -3: "VEGAS_EWORKSPACE",
-                -4: "VEGAS_EHIP", -5: "VEGAS_ENONFINITE", -6: "VEGAS_EUNSUPPORTED"}
+                -4: "VEGAS_EHIP", -5: "VEGAS_ENONFINITE", -6: "VEGAS_EUNSUPPORTED",
+                -7: "VEGAS_ECOMPILE"}
 
-GAUSS, BIMODAL, GENZ_DISC, GENZ_PEAK = 0, 1, 2, 3
+GAUSS, BIMODAL, GENZ_DISC, GENZ_PEAK, USER = 0, 1, 2, 3, 4
 FP64, FP32_MIXED = 0, 1
 CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST = 1, 2, 3, 4, 8, 16
 
 # every symbol include/vegas.h declares
 EXPORTS = [
-    "vegas_workspace_size", "vegas_init_grid", "vegas_iterate", "vegas_refine", "vegas_result",
+    "vegas_workspace_size", "vegas_init_grid", "vegas_init_user", "vegas_user_compile", "vegas_iterate", "vegas_refine", "vegas_result",
     "vegas_reset_results", "vegas_set_params_device", "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
     "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
@@ -77,6 +78,8 @@ def lib() -> ctypes.CDLL:
     sig = {
         "vegas_workspace_size": [P(Desc), P(sz)],
         "vegas_init_grid": [P(vp), P(Desc), vp, sz, vp],
+        "vegas_init_user": [P(vp), P(Desc), ctypes.c_char_p, vp, sz, vp],
+        "vegas_user_compile": [ctypes.c_char_p, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],
         "vegas_refine": [vp, vp],
         "vegas_result": [vp, P(Result), vp],

@@ -84,6 +84,8 @@ vegas_status check_batch(const vegas_desc* descs, const int64_t* n_events, int32
     for (int p = 0; p < n; ++p) {
         vegas_status st = check_desc(&descs[p]);
         if (st != VEGAS_OK) return fail(st, "problem %d: %s", p, g_err.c_str());
+        if (descs[p].integrand == VEGAS_USER)
+            return fail(VEGAS_EUNSUPPORTED, "problem %d: user integrands run as single contexts, not in batches", p);
         if (descs[p].integrand != descs[0].integrand || descs[p].precision != descs[0].precision)
             return fail(VEGAS_EINVAL, "problem %d: all problems of a batch share one integrand kind and precision", p);
         if (n_events[p] < 2 || n_events[p] > (int64_t(1) << 40))

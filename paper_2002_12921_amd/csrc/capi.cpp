@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "capi_util.hpp"
+#include "rtc.hpp"
 #include "vegas_internal.hpp"
 
 using namespace vegas;
@@ -39,7 +40,7 @@ int expected_params(int kind, int d)
     case VEGAS_GENZ_DISC:
     case VEGAS_GENZ_PEAK: return 2 * d;
     }
-    return -1;
+    return -1;  // unknown, or VEGAS_USER (the caller's count)
 }
 
 vegas_status check_params(int kind, int d, const double* q)
@@ -64,12 +65,22 @@ vegas_status check_desc(const vegas_desc* d)
     if (d->dim < 1 || d->dim > kMaxDim) return fail(VEGAS_EINVAL, "dim must be in [1, %d] (got %d)", kMaxDim, d->dim);
     if (d->n_bins < 2 || d->n_bins > kMaxBins)
         return fail(VEGAS_EINVAL, "n_bins must be in [2, %d] (got %d)", kMaxBins, d->n_bins);
-    if (d->integrand < VEGAS_GAUSS || d->integrand > VEGAS_GENZ_PEAK)
+    if (d->integrand < VEGAS_GAUSS || d->integrand > VEGAS_USER)
         return fail(VEGAS_EINVAL, "unknown integrand %d", d->integrand);
     if (d->precision != VEGAS_FP64 && d->precision != VEGAS_FP32_MIXED)
         return fail(VEGAS_EINVAL, "unknown precision %d", d->precision);
     if (!(d->alpha >= 0.0) || !std::isfinite(d->alpha)) return fail(VEGAS_EINVAL, "alpha must be finite and >= 0");
     if (d->problem < 0 || d->problem >= (1 << 24)) return fail(VEGAS_EINVAL, "problem must be in [0, 2^24)");
+    if (d->integrand == VEGAS_USER) {
+        if (d->precision != VEGAS_FP64) return fail(VEGAS_EUNSUPPORTED, "user integrands run in VEGAS_FP64 only");
+        if (d->n_params < 0 || d->n_params > kMaxParams)
+            return fail(VEGAS_EINVAL, "a user integrand takes 0..%d params (got %d)", kMaxParams, d->n_params);
+        if (d->n_params > 0 && !d->params) return fail(VEGAS_EINVAL, "params is NULL");
+        const size_t lds = lds_bytes(FP64, USER, d->dim, d->n_bins) + 128;
+        if (lds > kLdsLimit)
+            return fail(VEGAS_EUNSUPPORTED, "dim*n_bins too large: %zu bytes of LDS per block (limit %zu)", lds, kLdsLimit);
+        return VEGAS_OK;
+    }
     const int np = expected_params(d->integrand, d->dim);
     if (d->n_params != np) return fail(VEGAS_EINVAL, "integrand %d at dim %d takes %d params (got %d)", d->integrand, d->dim, np, d->n_params);
     if (!d->params) return fail(VEGAS_EINVAL, "params is NULL");
@@ -106,6 +117,11 @@ struct vegas_ctx {
     bool timing = false;
     std::vector<hipEvent_t> tev;  // 3 per recorded call
     int n_timed = 0;
+    // VEGAS_USER: the runtime-compiled module and its kernels
+    int n_params = 0;
+    hipModule_t umod = nullptr;
+    hipFunction_t usample[2] = {nullptr, nullptr};  // with, without histograms
+    hipFunction_t udump = nullptr;
 };
 
 namespace {
@@ -142,6 +158,17 @@ int sample_blocks(const vegas_ctx* c, int64_t n)
     if (nb < 1) nb = 1;
     if (nb > kMaxBlocks) nb = kMaxBlocks;
     return nb;
+}
+
+// LDS of the runtime-compiled event kernel: table, histogram replicas, wave partials.
+size_t user_lds(int d, int N, int rep, bool hist)
+{
+    return lds_bytes(FP64, USER, d, N, hist ? rep : 0) + sizeof(double) * (kBlock / 64);
+}
+
+size_t event_lds(const vegas_ctx* c, int rep, bool hist)
+{
+    return c->kind == USER ? user_lds(c->d, c->N, rep, hist) : sample_lds(c->prec, c->kind, c->d, c->N, rep, hist);
 }
 
 SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
@@ -191,6 +218,17 @@ MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
     return a;
 }
 
+// The event kernel of a context: built-in, or the runtime-compiled one.
+hipError_t launch_event_kernel(const vegas_ctx* c, const SampleArgs& a, int blocks, hipStream_t s)
+{
+    if (c->kind != USER) return launch_sample(c->prec, c->kind, a, blocks, c->threads, s);
+    const bool hist = a.hist != 0;
+    const double* params = c->P.params;
+    void* args[] = {const_cast<SampleArgs*>(&a), const_cast<double**>(&params)};
+    return hipModuleLaunchKernel(c->usample[hist ? 0 : 1], unsigned(blocks), 1, 1, unsigned(c->threads), 1, 1,
+                                 unsigned(event_lds(c, 1 << a.hrep_log2, hist)), s, args, nullptr);
+}
+
 vegas_status copy_out(vegas_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t s)
 {
     if (bytes > c->pinned_bytes) return fail(VEGAS_EINVAL, "internal: staging buffer too small");
@@ -226,13 +264,22 @@ vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes)
     return VEGAS_OK;
 }
 
-vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws, size_t ws_bytes,
-                             vegas_stream_t stream)
+}  // extern "C"
+
+namespace {
+
+// Context creation shared by vegas_init_grid and vegas_init_user (source:
+// the user integrand's code, NULL for the built-in integrands).
+vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* source, void* dev_ws, size_t ws_bytes,
+                      vegas_stream_t stream)
 {
     if (!out) return fail(VEGAS_EINVAL, "out is NULL");
     *out = nullptr;
     vegas_status st = check_desc(desc);
     if (st != VEGAS_OK) return st;
+    if ((desc->integrand == VEGAS_USER) != (source != nullptr))
+        return fail(VEGAS_EINVAL, source ? "vegas_init_user needs integrand VEGAS_USER"
+                                         : "VEGAS_USER contexts are created with vegas_init_user");
     const Layout L = make_layout(desc->dim, desc->n_bins);
     if (!dev_ws) return fail(VEGAS_EWORKSPACE, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0) return fail(VEGAS_EWORKSPACE, "workspace must be 256-byte aligned");
@@ -250,9 +297,11 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     c->ws = dev_ws;
     c->L = L;
     c->P = problem_ptrs(dev_ws, L);
+    c->n_params = desc->n_params;
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto bail = [&](vegas_status e) {
         if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->umod) (void)hipModuleUnload(c->umod);
         delete c;
         return e;
     };
@@ -260,6 +309,19 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     if ((he = hipGetDevice(&c->device)) != hipSuccess ||
         (he = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "device query: %s", hipGetErrorString(he)));
+    if (source) {
+        std::string code, log;
+        st = rtc_compile(source, c->d, code, log);
+        if (st != VEGAS_OK) return bail(st);
+        if ((he = hipModuleLoadData(&c->umod, code.data())) != hipSuccess) {
+            c->umod = nullptr;
+            return bail(fail(VEGAS_EHIP, "hipModuleLoadData: %s", hipGetErrorString(he)));
+        }
+        if ((he = hipModuleGetFunction(&c->usample[0], c->umod, "vegas_user_sample")) != hipSuccess ||
+            (he = hipModuleGetFunction(&c->usample[1], c->umod, "vegas_user_sample_nohist")) != hipSuccess ||
+            (he = hipModuleGetFunction(&c->udump, c->umod, "vegas_user_dump")) != hipSuccess)
+            return bail(fail(VEGAS_EHIP, "hipModuleGetFunction: %s", hipGetErrorString(he)));
+    }
     // Launch shape of the event kernel: block size and histogram replicas.
     // Score = resident waves per CU x a replica factor x a block-size factor.
     // The factors come from the d = 8 workload on gfx950: fewer replicas leave
@@ -272,9 +334,17 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
     double best = -1.0;
     int per_cu = 1;
     for (int th : {1024, 512, 256}) {
+        if (source && th > kUserThreads) continue;
         for (int l2 = 4; l2 >= 0; --l2) {
-            if (sample_lds(c->prec, c->kind, c->d, c->N, 1 << l2) > kLdsLimit) continue;
-            const int bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1 << l2);
+            const size_t lds = event_lds(c, 1 << l2, true);
+            if (lds > kLdsLimit) continue;
+            int bpc = 1;
+            if (!source) {
+                bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1 << l2);
+            } else if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, c->usample[0], th, lds) != hipSuccess ||
+                       bpc < 1) {
+                bpc = 1;
+            }
             const double score = double(bpc * th / 64) * kRepFactor[l2] * (th == 256 ? 0.92 : 1.0);
             if (score > best + 1e-9) {
                 best = score;
@@ -292,13 +362,47 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
         return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
     }
     const size_t pbytes = sizeof(double) * desc->n_params;
-    if ((he = hipMemcpyAsync(c->P.params, desc->params, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+    if ((pbytes > 0 && (he = hipMemcpyAsync(c->P.params, desc->params, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess) ||
         (he = launch_init_state(c->P, c->d, c->N, c->L.pstride, s)) != hipSuccess ||
         (he = launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s)) != hipSuccess ||
         (he = launch_build_tables(c->P, c->kind, c->d, c->N, s)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "init: %s", hipGetErrorString(he)));
     *out = c;
     return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws, size_t ws_bytes,
+                             vegas_stream_t stream)
+{
+    return init_ctx(out, desc, nullptr, dev_ws, ws_bytes, stream);
+}
+
+vegas_status vegas_init_user(vegas_ctx** out, const vegas_desc* desc, const char* source, void* dev_ws,
+                             size_t ws_bytes, vegas_stream_t stream)
+{
+    if (!source) {
+        if (out) *out = nullptr;
+        return fail(VEGAS_EINVAL, "source is NULL");
+    }
+    return init_ctx(out, desc, source, dev_ws, ws_bytes, stream);
+}
+
+vegas_status vegas_user_compile(const char* source, int32_t dim, char* log, size_t log_bytes)
+{
+    if (!source) return fail(VEGAS_EINVAL, "source is NULL");
+    if (dim < 1 || dim > kMaxDim) return fail(VEGAS_EINVAL, "dim must be in [1, %d] (got %d)", kMaxDim, dim);
+    std::string code, msg;
+    const vegas_status st = rtc_compile(source, dim, code, msg);
+    if (log && log_bytes > 0) {
+        const size_t n = std::min(msg.size(), log_bytes - 1);
+        std::memcpy(log, msg.data(), n);
+        log[n] = '\0';
+    }
+    return st;
 }
 
 vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
@@ -329,7 +433,7 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     const SampleArgs a = sample_args(c, e0, n, no_hist);
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
-    VEGAS_HIP(launch_sample(c->prec, c->kind, a, blocks, c->threads, s));
+    VEGAS_HIP(launch_event_kernel(c, a, blocks, s));
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
     int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
              ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0) | (no_hist ? MERGE_NO_HIST : 0);
@@ -365,7 +469,7 @@ vegas_status vegas_time_event_kernel(vegas_ctx* c, int64_t n, int32_t reps, int3
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he == hipSuccess) he = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_sample(c->prec, c->kind, a, blocks, c->threads, s);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_event_kernel(c, a, blocks, s);
     if (he == hipSuccess) he = hipEventRecord(e1, s);
     // the launches added into the histogram accumulators: clear them
     if (he == hipSuccess) he = launch_zero(c->P.hslots, size_t(kHistSlots) * c->d * c->N, s);
@@ -423,7 +527,9 @@ vegas_status vegas_set_params_device(vegas_ctx* c, const void* dev_params, int32
                                      vegas_stream_t stream)
 {
     if (!c || !dev_params) return fail(VEGAS_EINVAL, "NULL argument");
-    if (n != expected_params(c->kind, c->d)) return fail(VEGAS_EINVAL, "expected %d params, got %d", expected_params(c->kind, c->d), n);
+    const int want = c->kind == USER ? c->n_params : expected_params(c->kind, c->d);
+    if (n != want) return fail(VEGAS_EINVAL, "expected %d params, got %d", want, n);
+    if (n == 0) return VEGAS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     VEGAS_HIP(launch_params_from(dev_params, n, is_fp32 ? 1 : 0, c->P.params, s));
     VEGAS_HIP(launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s));
@@ -484,6 +590,16 @@ vegas_status vegas_dump_events(vegas_ctx* c, int64_t iteration, int64_t first, i
     a.key1 = uint32_t(c->seed >> 32);
     a.d = c->d;
     a.N = c->N;
+    if (c->kind == USER) {
+        // one event per thread, 256 threads, the FP64 table in LDS
+        const uint64_t blocks = std::min<uint64_t>((a.n + 255) / 256, 4096);
+        const double* params = c->P.params;
+        void* args[] = {&a, const_cast<double**>(&params)};
+        VEGAS_HIP(hipModuleLaunchKernel(c->udump, unsigned(blocks), 1, 1, 256, 1, 1,
+                                        unsigned(sizeof(double2) * c->d * c->N), static_cast<hipStream_t>(stream), args,
+                                        nullptr));
+        return VEGAS_OK;
+    }
     VEGAS_HIP(launch_dump(c->prec, c->kind, a, static_cast<hipStream_t>(stream)));
     return VEGAS_OK;
 }
@@ -614,7 +730,7 @@ vegas_status vegas_set_hist_replicas(vegas_ctx* c, int32_t replicas)
     while ((1 << l2) < replicas) ++l2;
     if (replicas < 0 || (1 << l2) != replicas || l2 > 4)
         return fail(VEGAS_EINVAL, "replicas must be 0 (automatic) or 1, 2, 4, 8, 16");
-    const size_t lds = sample_lds(c->prec, c->kind, c->d, c->N, replicas);
+    const size_t lds = event_lds(c, replicas, true);
     if (lds > kLdsLimit) return fail(VEGAS_EUNSUPPORTED, "%d replicas need %zu bytes of LDS", replicas, lds);
     c->hrep_user = l2;
     return VEGAS_OK;
@@ -677,6 +793,7 @@ vegas_status vegas_destroy(vegas_ctx* c)
     if (!c) return VEGAS_OK;
     free_events(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->umod) (void)hipModuleUnload(c->umod);
     delete c;
     return VEGAS_OK;
 }

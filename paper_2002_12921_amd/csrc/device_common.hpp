@@ -2,11 +2,19 @@
 // binning, the piecewise-linear map, the integrands and block reductions.
 #pragma once
 
-#include <type_traits>
-
 #include "vegas_internal.hpp"
 
 namespace vegas {
+
+// Type selection (std::conditional, which the runtime compiler lacks).
+template <bool B, class T, class F>
+struct pick_type {
+    using type = T;
+};
+template <class T, class F>
+struct pick_type<false, T, F> {
+    using type = F;
+};
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, sec. 3.2): ten rounds of
@@ -185,7 +193,7 @@ struct EventEval {
         // of the exponent) and in FP64 beyond, where that grows past the
         // method's tolerance
         constexpr bool kQ32 = !P::is64 && DMAX <= 8;
-        using q_t = typename std::conditional<kQ32, float, double>::type;
+        using q_t = typename pick_type<kQ32, float, double>::type;
         real w = real(1);
         real sa = real(0), sb = real(0);  // FP64 path: GAUSS/BIMODAL sums of squares; DISC: sum c u
         q_t qa = q_t(0), qb = q_t(0);     // FP32 path: the same sums

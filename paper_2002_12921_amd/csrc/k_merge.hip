@@ -75,6 +75,9 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
             c->p1_64[i] = cc;
             c->p2_64[i] = c->cA64[i] = aa;
         }
+    } else if (kind == USER) {
+        // the caller's f carries its own normalisation; C = N^d
+        Cf = 1.0;
     } else {
         // nu prod 1/(c^-2 + u^2) = [nu prod c^2] prod 1/(1 + c^2 u^2)
         Cf = 1.0;

@@ -1,0 +1,194 @@
+// Event and dump kernels for an integrand compiled at run time from the
+// caller's source (the paper's route for integrands written in C, C++ or GPU
+// code and linked into the integrator, sec. 2.3).  This header is not built
+// with the library: the host hands it, with vegas_internal.hpp and
+// device_common.hpp, to the runtime compiler once per context, after the
+// caller's source, with
+//   VEGAS_DIM      the dimension d (a compile-time constant, so the point
+//                  stays in registers and the caller's loops unroll),
+//   VEGAS_THREADS  the largest block the event kernel is launched with.
+// The caller's source defines
+//   __device__ double vegas_integrand(const double* x, int dim, const double* params)
+// evaluated at the mapped point x[0..d-1] in [0,1)^d; params is the context's
+// parameter array in device memory.
+//
+// Everything but the integrand is the FP64 path of the built-in event kernel:
+// the same Philox words, exact bins, map x_i = E_b + delta W_b and Jacobian
+// N^d prod W_b, the same grouped-Kahan sums of v = f w and v^2, and the same
+// per-dimension, per-bin histograms of v^2 (LDS replicas, then the block's
+// histogram added into slot blockIdx mod kHistSlots), so the reduction,
+// refinement and combination kernels of the library serve it unchanged.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace vegas {
+namespace user {
+
+constexpr int D = VEGAS_DIM;
+static_assert(D >= 1 && D <= kMaxDim, "VEGAS_DIM out of range");
+
+__device__ __forceinline__ BinConsts bin_consts(int N)
+{
+    BinConsts bc;
+    bc.mul = uint32_t(N);
+    bc.add = uint32_t(N) >> 1;
+    bc.h64 = (N & 1) ? 0x1p-33 : 0.0;
+    return bc;
+}
+
+// Point, bins and width product of one event.  Dimension i takes word i mod 4
+// of the Philox block of group i div 4; delta = (lo + h)/2^32 is exact, and
+// x_i = fma(delta, W_b, E_b) as in the built-in FP64 path.
+struct Event {
+    int b[D];
+    double del[D];
+    double x[D];
+    double wp;
+
+    __device__ __forceinline__ void run(const double2* __restrict__ tab, const BinConsts& bc, uint64_t e,
+                                        uint32_t t, uint32_t ctr3, uint32_t key0, uint32_t key1, int N)
+    {
+#pragma clang fp contract(off)
+        const uint32_t elo = uint32_t(e), ehi = uint32_t(e >> 32);
+        double w = 1.0;
+#pragma unroll
+        for (int g = 0; g < (D + 3) / 4; ++g) {
+            const U4 k = philox4x32_10(elo, ehi, t, ctr3 + uint32_t(g), key0, key1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * g + q;
+                if (i < D) {
+                    int bi;
+                    uint32_t lo;
+                    bin_words(k.w[q], bc, bi, lo);
+                    const double2 tb = (tab + i * N)[bi];
+                    const double dl = fma(double(lo), 0x1p-32, bc.h64);
+                    b[i] = bi;
+                    del[i] = dl;
+                    x[i] = fma(dl, tb.y, tb.x);
+                    w *= tb.y;
+                }
+            }
+        }
+        wp = w;
+    }
+};
+
+// LDS: table double2 [d][N] (128-byte aligned), histogram [d][N][rep]
+// (HIST only), then the block reduction's wave partials.
+template <bool HIST>
+__device__ __forceinline__ void sample(const SampleArgs& a, const double* __restrict__ params)
+{
+    extern __shared__ __align__(128) unsigned char smem[];
+    const int N = a.N;
+    const int dN = D * N;
+    const size_t tab_bytes = (size_t(dN) * sizeof(double2) + 127) & ~size_t(127);
+    const int rl2 = a.hrep_log2, rep = 1 << rl2;
+    const int lrep = int(threadIdx.x) & (rep - 1);
+    const size_t hist_bytes = HIST ? size_t(dN) * rep * sizeof(double) : 0;
+    double2* tab = reinterpret_cast<double2*>(smem);
+    double* hist = reinterpret_cast<double*>(smem + tab_bytes);
+    double* red = reinterpret_cast<double*>(smem + tab_bytes + hist_bytes);
+
+    const double2* gtab = static_cast<const double2*>(a.tab);
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
+    if constexpr (HIST)
+        for (int k = threadIdx.x; k < dN * rep; k += blockDim.x) hist[k] = 0.0;
+    __syncthreads();
+
+    const BinConsts bc = bin_consts(N);
+    const double C = a.cst->C;  // N^d
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    double g1 = 0.0, g2 = 0.0;
+    int ng = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t k = uint64_t(threadIdx.x) * gridDim.x + blockIdx.x; k < a.n; k += stride) {
+        Event ev;
+        ev.run(tab, bc, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, N);
+        const double f = vegas_integrand(ev.x, D, params);
+        double v, v2;
+        {
+#pragma clang fp contract(off)
+            v = f * ev.wp * C;
+            v2 = v * v;
+            g1 += v;
+            g2 += v2;
+        }
+        if (++ng == kGroup) {
+            kahan_add(s1, c1, g1);
+            kahan_add(s2, c2, g2);
+            g1 = g2 = 0.0;
+            ng = 0;
+        }
+        if constexpr (HIST) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) lds_atomic_add(&(hist + (i * N << rl2))[(ev.b[i] << rl2) | lrep], v2);
+        }
+    }
+    kahan_add(s1, c1, g1);
+    kahan_add(s2, c2, g2);
+
+    // block_sum synchronises, which also completes every histogram atomic
+    const double S1 = block_sum(s1 - c1, red);
+    const double S2 = block_sum(s2 - c2, red);
+    double* row = a.partials + size_t(blockIdx.x) * a.pstride;
+    if (threadIdx.x == 0) {
+        row[0] = S1;
+        row[1] = S2;
+    }
+    if constexpr (HIST) {
+        double* slot = a.hslots + size_t(blockIdx.x % kHistSlots) * dN;
+        for (int k = threadIdx.x; k < dN; k += blockDim.x) {
+            const int base = k << rl2;
+            double h = 0.0;
+            for (int r = 0; r < rep; ++r) h += hist[base + r];
+            atomicAdd(&slot[k], h);
+        }
+    }
+}
+
+}  // namespace user
+}  // namespace vegas
+
+extern "C" __global__ __launch_bounds__(VEGAS_THREADS) void vegas_user_sample(vegas::SampleArgs a,
+                                                                              const double* __restrict__ params)
+{
+    vegas::user::sample<true>(a, params);
+}
+
+extern "C" __global__ __launch_bounds__(VEGAS_THREADS) void vegas_user_sample_nohist(vegas::SampleArgs a,
+                                                                                     const double* __restrict__ params)
+{
+    vegas::user::sample<false>(a, params);
+}
+
+// Per-event records b[d], delta[d], x[d], w, f (w = N^d prod W_b), one event
+// per thread; LDS holds the table.
+extern "C" __global__ __launch_bounds__(256) void vegas_user_dump(vegas::DumpArgs a, const double* __restrict__ params)
+{
+    using namespace vegas;
+    constexpr int D = user::D;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.N;
+    double2* tab = reinterpret_cast<double2*>(smem);
+    const double2* gtab = static_cast<const double2*>(a.tab);
+    for (int k = threadIdx.x; k < D * N; k += blockDim.x) tab[k] = gtab[k];
+    __syncthreads();
+    const BinConsts bc = user::bin_consts(N);
+    const double Cw = a.cst->Cw;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < a.n; k += stride) {
+        user::Event ev;
+        ev.run(tab, bc, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, N);
+        double* row = a.out + k * size_t(3 * D + 2);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            row[i] = double(ev.b[i]);
+            row[D + i] = ev.del[i];
+            row[2 * D + i] = ev.x[i];
+        }
+        row[3 * D] = ev.wp * Cw;
+        row[3 * D + 1] = vegas_integrand(ev.x, D, params);
+    }
+}

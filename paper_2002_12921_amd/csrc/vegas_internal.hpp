@@ -1,10 +1,20 @@
 // Internal declarations shared by the HIP kernels and the C-ABI host code.
+// The device part is also handed to the runtime compiler for user integrands
+// (__HIPCC_RTC__ defined): there the HIP device API is built in and only the
+// fixed-width integer names are missing.
 #pragma once
 
+#ifdef __HIPCC_RTC__
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::uint64_t uint64_t;
+#else
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#endif
 
 namespace vegas {
 
@@ -20,7 +30,8 @@ constexpr int kHistSlots = 8;
 constexpr int kMergeThreads = 1024; // threads per block of the reduction kernel
 constexpr size_t kLdsLimit = 160 * 1024;
 
-enum Kind { GAUSS = 0, BIMODAL = 1, GENZ_DISC = 2, GENZ_PEAK = 3 };
+// USER: an integrand compiled at run time from the caller's source (FP64 only)
+enum Kind { GAUSS = 0, BIMODAL = 1, GENZ_DISC = 2, GENZ_PEAK = 3, USER = 4 };
 enum Prec { FP64 = 0, FP32 = 1 };
 
 // Derived per-problem constants, computed on the device from the raw FP64
@@ -259,6 +270,7 @@ struct BatchArgs {
     int hrep_log2;      // log2 of the histogram replicas per bin
 };
 
+#ifndef __HIPCC_RTC__
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).
 
@@ -287,5 +299,6 @@ int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int thread
 hipError_t launch_batch_finish(const BatchArgs& a, int dmax, int kind, int rec_idx, int flags, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind, hipStream_t s);
 hipError_t launch_batch_combine(const BatchArgs& a, int n_rec, hipStream_t s);
+#endif
 
 }  // namespace vegas

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import check, lib
 
 INTEGRANDS = {"gauss": _lib.GAUSS, "bimodal": _lib.BIMODAL,
-              "genz_disc": _lib.GENZ_DISC, "genz_peak": _lib.GENZ_PEAK}
+              "genz_disc": _lib.GENZ_DISC, "genz_peak": _lib.GENZ_PEAK, "user": _lib.USER}
 PRECISIONS = {"fp64": _lib.FP64, "fp32_mixed": _lib.FP32_MIXED, "mixed": _lib.FP32_MIXED}
 
 
@@ -29,21 +29,38 @@ def make_desc(dim: int, n_bins: int, integrand, params: Sequence[float], precisi
     """Returns (Desc, keep-alive params array)."""
     kind = INTEGRANDS[integrand] if isinstance(integrand, str) else int(integrand)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64)).reshape(-1)
     d = _lib.Desc(dim, n_bins, kind, prec, seed, alpha,
                   p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(p), problem)
     return d, p
 
 
-class Vegas:
-    """One adaptive Vegas integration on the current HIP device."""
+def compile_user(source: str, dim: int) -> tuple[bool, str]:
+    """Compile a user integrand for dimension dim without a device (see
+    vegas_user_compile): (compiled?, compiler messages)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = lib().vegas_user_compile(source.encode(), int(dim), buf, len(buf))
+    if st not in (_lib.VEGAS_OK, _lib.VEGAS_ECOMPILE):
+        check(st, "user_compile")
+    return st == _lib.VEGAS_OK, buf.value.decode(errors="replace")
 
-    def __init__(self, dim: int, n_bins: int = 50, integrand="gauss",
+
+class Vegas:
+    """One adaptive Vegas integration on the current HIP device.
+
+    source: HIP device code defining
+    ``__device__ double vegas_integrand(const double* x, int dim, const double* params)``
+    (a user integrand, compiled at run time; integrand and precision then
+    default to "user" and "fp64", and params to none)."""
+
+    def __init__(self, dim: int, n_bins: int = 50, integrand=None,
                  params: Optional[Sequence[float]] = None, precision="fp64", seed: int = 0,
                  alpha: float = 1.5, problem: int = 0, device=None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, source: Optional[str] = None):
+        if integrand is None:
+            integrand = "user" if source is not None else "gauss"
         if params is None:
-            params = [0.1] + [0.5] * dim
+            params = [] if source is not None else [0.1] + [0.5] * dim
         self.dim, self.n_bins = dim, n_bins
         self.desc, self._params = make_desc(dim, n_bins, integrand, params, precision, seed,
                                             alpha, problem)
@@ -55,9 +72,14 @@ class Vegas:
         with torch.cuda.device(self.device):
             self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
             self._ctx = ctypes.c_void_p()
-            check(L.vegas_init_grid(ctypes.byref(self._ctx), ctypes.byref(self.desc),
-                                    ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
-                                    self._s()), "init_grid")
+            if source is not None:
+                check(L.vegas_init_user(ctypes.byref(self._ctx), ctypes.byref(self.desc), source.encode(),
+                                        ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                        self._s()), "init_user")
+            else:
+                check(L.vegas_init_grid(ctypes.byref(self._ctx), ctypes.byref(self.desc),
+                                        ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                        self._s()), "init_grid")
 
     # -- helpers -----------------------------------------------------------
     def _s(self):

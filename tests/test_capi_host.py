@@ -103,3 +103,62 @@ def test_null_context_calls():
     assert L.vegas_result(None, ctypes.byref(r), None) == _lib.VEGAS_EINVAL
     assert L.vegas_destroy(None) == _lib.VEGAS_OK
     assert L.vegas_batch_destroy(None) == _lib.VEGAS_OK
+
+
+GOOD_SRC = """
+__device__ double vegas_integrand(const double* x, int dim, const double* p)
+{
+    double s = p[0];
+    for (int i = 0; i < dim; ++i) s += x[i] * x[i];
+    return exp(-s);
+}
+"""
+
+
+def test_user_compile_on_host():
+    """The runtime compiler needs no device: a valid integrand compiles for
+    every dimension class; a broken one reports VEGAS_ECOMPILE with the
+    compiler's message located in the caller's own line numbering."""
+    from paper_2002_12921_amd import compile_user
+    for d in (1, 4, 13, 64):
+        ok, log = compile_user(GOOD_SRC, d)
+        assert ok, log
+    ok, log = compile_user("__device__ double vegas_integrand(const double* x, int d, const double* p)\n"
+                           "{\n    return x[0] +* 2;\n}\n", 3)
+    assert not ok and "integrand:3:" in log and "error" in log
+    ok, log = compile_user("__device__ double not_the_entry(const double* x) { return 1.0; }\n", 2)
+    assert not ok and "vegas_integrand" in log
+    L = _lib.lib()
+    assert L.vegas_user_compile(None, 3, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(GOOD_SRC.encode(), 0, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(GOOD_SRC.encode(), 65, None, 0) == _lib.VEGAS_EINVAL
+    buf = ctypes.create_string_buffer(8)  # the log is cut to the buffer, NUL-terminated
+    assert L.vegas_user_compile(b"garbage(", 2, buf, 8) == _lib.VEGAS_ECOMPILE
+    assert len(buf.value) <= 7
+
+
+def test_user_desc_checks():
+    L = _lib.lib()
+    d, keep = make_desc(5, 40, "user", [], "fp64")
+    st, n = _size(d)
+    assert st == _lib.VEGAS_OK and n > 0
+    d, keep = make_desc(5, 40, "user", [1.0] * 129, "fp64")
+    assert _size(d)[0] == _lib.VEGAS_OK
+    d, keep = make_desc(5, 40, "user", [1.0] * 130, "fp64")
+    assert _size(d)[0] == _lib.VEGAS_EINVAL
+    d, keep = make_desc(5, 40, "user", [], "fp32_mixed")
+    assert _size(d)[0] == _lib.VEGAS_EUNSUPPORTED
+    ctx = ctypes.c_void_p()
+    u, keep = make_desc(5, 40, "user", [], "fp64")
+    g, keep2 = make_desc(4, 50, "gauss", [0.1] + [0.5] * 4)
+    # a user kind needs vegas_init_user, and vegas_init_user a user kind and a source
+    assert L.vegas_init_grid(ctypes.byref(ctx), ctypes.byref(u), ctypes.c_void_p(4096), 1 << 30, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_init_user(ctypes.byref(ctx), ctypes.byref(g), GOOD_SRC.encode(), ctypes.c_void_p(4096), 1 << 30,
+                             None) == _lib.VEGAS_EINVAL
+    assert L.vegas_init_user(ctypes.byref(ctx), ctypes.byref(u), None, ctypes.c_void_p(4096), 1 << 30,
+                             None) == _lib.VEGAS_EINVAL
+    assert ctx.value is None
+    # batches take built-in integrands only
+    n_ev = (ctypes.c_int64 * 1)(1000)
+    nb = ctypes.c_size_t()
+    assert L.vegas_batch_workspace_size(ctypes.byref(u), n_ev, 1, ctypes.byref(nb)) == _lib.VEGAS_EUNSUPPORTED
