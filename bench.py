@@ -8,7 +8,8 @@ statistics -> refinement, all on the device.  The headline value is events/s
 of the FP32-mixed path; the FP64 path is timed the same way beside it.
 
 Also reported: the event kernel's roofline (VALU issue bound), the whole
-5 adaptation + 5 accumulation schedule for both precisions, and the CPU
+5 adaptation + 5 accumulation schedule for both precisions, the same
+Gaussian as a user integrand compiled at run time (FP64), and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -109,19 +110,26 @@ def time_accumulation(precision: str, steps: int, warmup: int):
     return {"ms_per_iteration": ms, "events_per_s": _events_per_s(ms)}
 
 
-def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0):
+def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas: int = 0,
+              source: str | None = None):
     """Two timed passes over `steps` adaptation iterations: the first with
     nothing but the HIP events around the whole region (the headline), the
     second with the library's events around each kernel of each step (their
     durations within a step; the event records themselves add a few
     microseconds each).  Then the event kernel alone: `steps` launches back
     to back between two events on its stream, whose duration per launch sets
-    the roofline figure."""
+    the roofline figure.  source: the same Gaussian as a user integrand
+    (compiled at run time; FP64), timed the same way."""
     import torch
     from paper_2002_12921_amd import Vegas
 
     params = [A] + [0.5] * D
-    v = Vegas(D, NBINS, "gauss", params, precision, seed=0, alpha=ALPHA)
+    t_init = time.perf_counter()
+    if source is None:
+        v = Vegas(D, NBINS, "gauss", params, precision, seed=0, alpha=ALPHA)
+    else:
+        v = Vegas(D, NBINS, params=params, source=source, seed=0, alpha=ALPHA)
+    init_s = time.perf_counter() - t_init
     if blocks:
         v.set_launch(blocks)
     if replicas:
@@ -155,6 +163,7 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
         "event_kernel_ms_in_step": sample_ms / n,
         "merge_kernel_ms_in_step": merge_ms / n,
         "launch": v.launch_info(),
+        "init_s": init_s,
     }
 
 
@@ -407,6 +416,10 @@ def main():
     c1 = None if args.mixed_only else c1_small(5)
     accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
                                           for p in ("fp32_mixed", "fp64")}
+    user = None
+    if not args.mixed_only:
+        from paper_2002_12921_amd import user_integrands
+        user = time_path("fp64", args.steps, args.warmup, source=user_integrands.GAUSSIAN)
 
     slots = alg_slots_per_event(D)
     t_k = mixed["event_kernel_ms"] * 1e-3
@@ -460,6 +473,12 @@ def main():
         out["differentiable_d8"] = c4
     if c1 is not None:
         out["gauss_d4_fp64_small"] = c1
+    if user is not None:
+        out["user_integrand_gauss_d8_fp64"] = {
+            "value": user["events_per_s"], "ms_per_step": user["ms_per_step"],
+            "event_kernel_ms": user["event_kernel_ms"], "launch": user["launch"],
+            "compile_and_init_s": user["init_s"],
+            "over_builtin_fp64": user["events_per_s"] / fp64["events_per_s"] if fp64 else None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]
