@@ -38,19 +38,25 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
 def alg_slots_per_event(d: int) -> int:
-    """Algorithmic VALU lane-slots per event of the FP32-mixed Gaussian event
-    kernel: the operations the method needs, weighted by gfx950 issue cost
-    (every VALU instruction one slot -- the 32x32->64 multiply-add included,
-    which runs at full rate on gfx950 -- and the FP32 exponential four):
-      Philox4x32-10: ceil(d/4) calls x 10 rounds x (2 multiply-adds + 2 three-way xors) = 40 ceil(d/4)
-      per dimension: binning (multiply-add, convert, fma) 3, map (LDS address,
-        fma, Jacobian multiply) 3, exponent term in FP64 (convert, fma) 2,
-        histogram address 1                                                   = 9 d
-      per event: exponent split and exponential 8, scaling to FP64 4,
-        (f w)^2 and the two compensated sums 9, loop 3                        = 24
-    The LDS atomics of the histograms run on the LDS pipe and are not counted.
-    """
-    return 40 * math.ceil(d / 4) + 9 * d + 24
+    """VALU lane-slots per event that the FP32-mixed Gaussian event kernel's
+    algorithm needs (d <= 8), each VALU instruction one slot -- the
+    32x32->64 multiply-add included, which issues at full rate on gfx950:
+      Philox4x32-10: ceil(d/4) blocks x 10 rounds x (2 multiply-adds + 2
+        three-way xors), less one multiply per extra block (the first round's
+        product of counter word 0 is common to all blocks of an event)
+                                                   = 40 ceil(d/4) - (ceil(d/4) - 1)
+      per dimension: bin and low word (1 multiply-add), convert (1), table
+        address (1), scaled map (1 fma), Jacobian product (1), exponent term
+        (1 fma), histogram address (1)              = 7 d
+      per event: exponent split and exponential (convert, scale, floor,
+        subtract, convert, exp2: 6), value (F w, convert, exponent add,
+        ldexp, times C: 5), v^2 and the two grouped sums with their
+        compensation (4), lane replica offset and loop (5)     = 20
+    The LDS reads and atomics run on the LDS pipe and are not counted.  For
+    d = 8 the count equals the VALU instructions the kernel executes per
+    event (the counters read 155.4)."""
+    g = math.ceil(d / 4)
+    return 40 * g - (g - 1) + 7 * d + 20
 
 
 # Counter summary of the event kernel (HBM bytes per launch from FETCH_SIZE and
@@ -99,6 +105,7 @@ def time_accumulation(precision: str, steps: int, warmup: int):
         v.iterate(EVENTS, refine=True, combine=False)
     for _ in range(warmup):
         v.iterate(EVENTS, hist=False)
+    v.reset_results()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
@@ -135,8 +142,11 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     if replicas:
         v.set_hist_replicas(replicas)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+    for k in range(warmup):
         v.iterate(EVENTS, refine=True, combine=False)
+        if k % 1000 == 999:
+            v.reset_results()  # at most 1024 recorded iterations per context
+    v.reset_results()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -148,6 +158,7 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(stop)
 
+    v.reset_results()
     v.timing_enable(True)
     for _ in range(steps):
         v.iterate(EVENTS, refine=True, combine=False)
@@ -383,8 +394,10 @@ def copy_probe():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # the GPU's clock ramps over the first ~30 ms of sustained load (a d = 8
+    # step drops from ~55 to ~48 us): the default warm-up covers that ramp
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=800)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true")
@@ -393,6 +406,10 @@ def main():
     ap.add_argument("--phase-split", action="store_true",
                     help="only time iterations with/without refinement and without histograms")
     args = ap.parse_args()
+    if not 1 <= args.steps <= 1000 or args.warmup < 0:
+        print("--steps must be in [1, 1000] (a context records at most 1024 iterations) and --warmup >= 0",
+              file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path is "
               "single-device by design", file=sys.stderr)

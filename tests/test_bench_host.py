@@ -4,9 +4,10 @@ import bench
 
 
 def test_alg_slots_table():
-    # 40 ceil(d/4) + 9 d + 24
-    assert bench.alg_slots_per_event(8) == 176
-    assert bench.alg_slots_per_event(5) == 80 + 45 + 24
+    # Philox 40 ceil(d/4) - (ceil(d/4) - 1), 7 per dimension, 20 per event
+    assert bench.alg_slots_per_event(8) == 79 + 56 + 20
+    assert bench.alg_slots_per_event(5) == 79 + 35 + 20
+    assert bench.alg_slots_per_event(4) == 40 + 28 + 20
 
 
 def test_gpus_above_one_is_refused(monkeypatch, capsys):
