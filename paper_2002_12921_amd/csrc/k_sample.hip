@@ -28,9 +28,20 @@ constexpr int kFixBins = 64;
 constexpr int kFixRepLog2 = 4;
 constexpr int kFixDimBytes = kFixBins << (kFixRepLog2 + 3);
 
+// Fewest waves per SIMD the register allocation must allow.  8 (64 VGPRs, two
+// 1024-thread blocks per CU) for the FP64 Gaussian, bimodal and product-peak
+// kernels up to d = 8: they then spill a few registers but issue from more
+// waves (d = 8 Gaussian: 64.2 against 67.2 us per 1e7 events).  4 elsewhere:
+// the discontinuous integrand and larger d would spill heavily, and the
+// FP32-mixed kernels reach 8 waves by themselves.
+template <class P, int KIND, int DMAX>
+struct MinWaves {
+    static constexpr int value = (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 8 : 4;
+};
+
 template <class P, int KIND, int DMAX, bool EXACT, int HM>
-// aim for 8 waves per SIMD (two blocks per CU) without spilling; accept 4
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sample(SampleArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<P, KIND, DMAX>::value, 8))) void k_sample(
+    SampleArgs a)
 {
     constexpr bool FIX = HM == kHistFixed;
     static_assert(!FIX || (EXACT && DMAX <= 8), "fixed layout: d <= 8 only");
