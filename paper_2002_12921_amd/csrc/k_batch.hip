@@ -13,8 +13,18 @@
 
 namespace vegas {
 
+// Fewest waves per SIMD the register allocation must allow: 6 for the
+// FP32-mixed kernel of the d <= 16 bucket (80 VGPRs, a few spilled; it then
+// runs 512-thread blocks, 3 per CU, instead of one 1024-thread block, and the
+// 256-problem batch gains ~5 %), 4 elsewhere.
+template <class P, int DMAX>
+struct BatchMinWaves {
+    static constexpr int value = (!P::is64 && DMAX == 16) ? 6 : 4;
+};
+
 template <class P, int KIND, int DMAX, bool HIST>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_sample(BatchArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMinWaves<P, DMAX>::value, 8))) void k_batch_sample(
+    BatchArgs a)
 {
     using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(128) unsigned char smem[];
