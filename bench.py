@@ -9,7 +9,8 @@ of the FP32-mixed path; the FP64 path is timed the same way beside it.
 
 Also reported: the event kernel's roofline (VALU issue bound), the whole
 5 adaptation + 5 accumulation schedule for both precisions, the same
-Gaussian as a user integrand compiled at run time (FP64), and the CPU
+Gaussian as a user integrand compiled at run time (FP64), the Genz
+discontinuous and product-peak integrands at d = 16, and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -309,6 +310,36 @@ def differentiable_c4(steps: int):
             "grad_mu0": float(mu.grad[0]), "grad_a": float(a.grad)}
 
 
+def genz_d16(steps: int, warmup: int):
+    """The paper's second workload: the Genz discontinuous and product-peak
+    integrands at d = 16 (workloads.genz16), 50 bins, 1e7 events per
+    adaptation iteration, in both precisions: events/s of the adaptation
+    step and the event kernel alone (back-to-back launches)."""
+    import torch
+    from paper_2002_12921_amd import Vegas, workloads
+
+    out = {}
+    for kind in ("genz_disc", "genz_peak"):
+        for prec in ("fp32_mixed", "fp64"):
+            v = Vegas(16, NBINS, kind, workloads.genz16(kind), prec, seed=0, alpha=ALPHA)
+            for _ in range(warmup):
+                v.iterate(EVENTS, refine=True, combine=False)
+            v.reset_results()
+            torch.cuda.synchronize()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(steps):
+                v.iterate(EVENTS, refine=True, combine=False)
+            stop.record()
+            torch.cuda.synchronize()
+            v.reset_results()
+            ms = start.elapsed_time(stop) / steps
+            out[f"{kind}_{prec}"] = {"ms_per_step": ms, "events_per_s": _events_per_s(ms),
+                                     "event_kernel_ms": v.time_event_kernel(EVENTS, steps),
+                                     "launch": v.launch_info()}
+    return out
+
+
 def c1_small(reps: int):
     """The d = 4 FP64 case: 10 iterations of 1e5 events, each refined after and
     all combined, call by call (best of `reps` runs; at this size the launches,
@@ -431,6 +462,7 @@ def main():
     c3 = None if args.mixed_only else c3_streamed()
     c4 = None if args.mixed_only else differentiable_c4(args.steps)
     c1 = None if args.mixed_only else c1_small(5)
+    genz = None if args.mixed_only else genz_d16(min(args.steps, 100), min(args.warmup, 100))
     accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
                                           for p in ("fp32_mixed", "fp64")}
     user = None
@@ -490,6 +522,8 @@ def main():
         out["differentiable_d8"] = c4
     if c1 is not None:
         out["gauss_d4_fp64_small"] = c1
+    if genz is not None:
+        out["genz_d16"] = genz
     if user is not None:
         out["user_integrand_gauss_d8_fp64"] = {
             "value": user["events_per_s"], "ms_per_step": user["ms_per_step"],

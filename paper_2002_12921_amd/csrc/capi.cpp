@@ -330,7 +330,13 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
     // per-block set-up and partial rows than they gain (7 x 256 threads with
     // 4 replicas ran 11 % slower than 3 x 512 with 8 in FP64).  Ties keep the
     // larger block and the more replicas.
-    static const double kRepFactor[5] = {0.5, 0.65, 0.8, 0.93, 1.0};  // 1, 2, 4, 8, 16 replicas
+    // Beyond d = 8 each event makes more histogram atomics per instruction and
+    // the replicas weigh more: at d = 16 (Genz, FP32-mixed) one block of 16
+    // replicas ran 14 % faster than three blocks of 4 and 3 % faster than two
+    // of 8, so the factors are steeper there.
+    static const double kRepFactorLow[5] = {0.5, 0.65, 0.8, 0.93, 1.0};   // 1, 2, 4, 8, 16 replicas
+    static const double kRepFactorHigh[5] = {0.1, 0.2, 0.35, 0.6, 1.0};
+    const double* kRepFactor = c->d > 8 ? kRepFactorHigh : kRepFactorLow;
     double best = -1.0;
     int per_cu = 1;
     for (int th : {1024, 512, 256}) {

@@ -449,9 +449,8 @@ def test_adjoint_c4_shape():
 
 
 def _genz_params(kind, d):
-    if kind == "genz_disc":
-        return list(np.linspace(0.5, 1.5, d)) + list(np.linspace(0.05, 0.3, d))
-    return list(np.linspace(2.0, 4.0, d)) + list(np.linspace(0.3, 0.7, d))
+    from paper_2002_12921_amd import workloads
+    return workloads.genz16(kind, d)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
