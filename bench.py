@@ -8,7 +8,8 @@ statistics -> refinement, all on the device.  The headline value is events/s
 of the FP32-mixed path; the FP64 path is timed the same way beside it.
 
 Also reported: the event kernel's roofline (VALU issue bound), the whole
-5 adaptation + 5 accumulation schedule for both precisions, the same
+5 adaptation + 5 accumulation schedule for both precisions, plain Monte
+Carlo iterations (uniform grid, no histograms, no refinement), the same
 Gaussian as a user integrand compiled at run time (FP64), the Genz
 discontinuous and product-peak integrands at d = 16, and the CPU
 oracle timed on a bounded sample of the same workload.
@@ -95,14 +96,15 @@ def _events_per_s(ms_per_step: float) -> float:
     return EVENTS / (ms_per_step * 1e-3)
 
 
-def time_accumulation(precision: str, steps: int, warmup: int):
+def time_accumulation(precision: str, steps: int, warmup: int, adapt: int = 5):
     """Accumulation iterations on a frozen (adapted) grid: no histograms and
-    no refinement, the rest of the path as in the adaptation step."""
+    no refinement, the rest of the path as in the adaptation step.  With
+    adapt = 0 the grid stays uniform: plain Monte Carlo."""
     import torch
     from paper_2002_12921_amd import Vegas
 
     v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
-    for _ in range(5):
+    for _ in range(adapt):
         v.iterate(EVENTS, refine=True, combine=False)
     for _ in range(warmup):
         v.iterate(EVENTS, hist=False)
@@ -465,6 +467,8 @@ def main():
     genz = None if args.mixed_only else genz_d16(min(args.steps, 100), min(args.warmup, 100))
     accum = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup)
                                           for p in ("fp32_mixed", "fp64")}
+    plain = None if args.mixed_only else {p: time_accumulation(p, args.steps, args.warmup, adapt=0)
+                                          for p in ("fp32_mixed", "fp64")}
     user = None
     if not args.mixed_only:
         from paper_2002_12921_amd import user_integrands
@@ -514,6 +518,8 @@ def main():
                               "exact": 0.99999999998770032}
     if accum is not None:
         out["accumulation_iteration"] = accum
+    if plain is not None:
+        out["plain_mc_uniform_grid"] = plain
     if batch is not None:
         out["batch256"] = batch
     if c3 is not None:
