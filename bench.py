@@ -196,8 +196,50 @@ def c2_schedule(precision: str):
         v.iterate(EVENTS, hist=False)
     r = v.result()
     wall = time.perf_counter() - t0
-    return {"integral": r["integral"], "sigma": r["sigma"], "chi2_dof": r["chi2_dof"],
-            "rel_err": r["sigma"] / r["integral"], "wall_ms": wall * 1e3}
+    out = {"integral": r["integral"], "sigma": r["sigma"], "chi2_dof": r["chi2_dof"],
+           "rel_err": r["sigma"] / r["integral"], "wall_ms": wall * 1e3}
+    try:
+        out.update(c2_schedule_graph(precision, r["integral"], r["sigma"]))
+    except RuntimeError as e:  # capture refused, or a replay that disagreed
+        out["graph_error"] = str(e)
+    return out
+
+
+def c2_schedule_graph(precision: str, integral: float, sigma: float, reps: int = 5):
+    """The same 10 iterations recorded once as a HIP graph (stream capture of
+    the library's launches) and replayed `reps` times, each replay from the
+    uniform grid: GPU time of the whole schedule without host launch gaps.
+    Every replay's combined result is checked against the eager run (equal
+    up to the rounding that the nondeterministic histogram sums leave in the
+    refined grids)."""
+    import torch
+    from paper_2002_12921_amd import Vegas
+
+    v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
+    E0 = v.edges()
+    s = torch.cuda.Stream()
+    v.stream = s
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(5):
+            v.iterate(EVENTS, refine=True, combine=False)
+        for _ in range(5):
+            v.iterate(EVENTS, hist=False)
+    ms, worst = [], 0.0
+    for _ in range(reps):
+        v.set_edges(E0)  # on s, before the replay
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        with torch.cuda.stream(s):  # replay() launches on the current stream
+            g.replay()
+        e1.record(s)
+        r = v.result()
+        ms.append(e0.elapsed_time(e1))
+        worst = max(worst, abs(r["integral"] - integral) / sigma)
+        if not worst <= 1e-6:
+            raise RuntimeError(f"graph replay differs from the eager schedule by {worst} sigma")
+    return {"graph_ms": min(ms), "graph_ms_all": ms, "graph_replay_minus_eager_in_sigma_max": worst}
 
 
 def batch_c5(reps: int):

@@ -654,3 +654,41 @@ def test_refine_damping_exponents(alpha):
     v.iterate(M, refine=True)
     H = v.last_iteration()[2]
     assert np.max(np.abs(v.edges() - oracle.refine(H, E, alpha))) <= 1e-12
+
+
+def test_graph_captured_iterations_replay():
+    """Single-problem iterations recorded as a HIP graph (stream capture of
+    the library's launches) and replayed three times, each from the uniform
+    grid with eager work in between: every replay gives the eager run's
+    combined result (to the rounding that nondeterministic histogram sums
+    leave in the refined grids)."""
+    d, N, M = 8, 50, 300_007
+    params = _gauss(d)
+    eager = Vegas(d, N, "gauss", params, "fp32_mixed", seed=3)
+    for _ in range(3):
+        eager.iterate(M, refine=True, combine=False)
+    for _ in range(2):
+        eager.iterate(M, hist=False)
+    ref = eager.result()
+    v = Vegas(d, N, "gauss", params, "fp32_mixed", seed=3)
+    E0 = v.edges()
+    s = torch.cuda.Stream()
+    v.stream = s
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(3):
+            v.iterate(M, refine=True, combine=False)
+        for _ in range(2):
+            v.iterate(M, hist=False)
+    for rep in range(3):
+        v.set_edges(E0)
+        with torch.cuda.stream(s):  # replay() launches on the current stream
+            g.replay()
+        r = v.result()
+        assert abs(r["integral"] - ref["integral"]) <= 1e-12 * abs(ref["integral"]), (rep, r, ref)
+        assert abs(r["sigma"] - ref["sigma"]) <= 1e-9 * ref["sigma"], (rep, r, ref)
+        assert r["n_combined"] == 2
+        # eager work between replays
+        eager.iterate(1000, hist=False, combine=False)
+        torch.cuda.synchronize()
