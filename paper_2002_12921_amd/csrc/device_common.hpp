@@ -59,7 +59,9 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // ---------------------------------------------------------------------------
 // Precision policies and grid-table entry types.
 //
-// FP64: table entry (E_b, E_{b+1} - E_b); x = E_b + delta * width, u = x - centre.
+// FP64: table entry (E_b - c, E_{b+1} - E_b) for the integrand's centre c, so
+//   u = x - c = fma(delta, width, E_b - c) is one fma (x itself is not formed;
+//   the centre is 0 for user integrands, whose table holds E_b).
 // FP32: the map works on u' = (x - c) S with S = 2^(ws + 32).  With
 //   delta = (lo + h)/2^32 (see bin_words) and W = RN32(width), the table entry is
 //     (RN32((E_b - c + h W / 2^32) S), W 2^ws),
@@ -138,8 +140,10 @@ struct EvalConsts {
             c64[i] = 0.0;
             c32[i] = 0.0f;
             if constexpr (P::is64) {
-                p1[i] = c->p1_64[i];
-                if constexpr (KIND != GAUSS) p2[i] = c->p2_64[i];
+                // the centres are in the table: GENZ c (DISC) or c^2 (PEAK),
+                // BIMODAL muB - muA
+                if constexpr (KIND == GENZ_DISC || KIND == GENZ_PEAK) p1[i] = c->p1_64[i];
+                if constexpr (KIND == BIMODAL) p2[i] = c->p2_64[i];
             } else {
                 if constexpr (KIND == GENZ_PEAK) p1[i] = real(sqrt(c->p1_64[i]) * ds);  // c_i / S
                 if constexpr (KIND == GENZ_DISC) {
@@ -219,10 +223,8 @@ struct EventEval {
                         if constexpr (P::is64) {
                             dl = fma(double(lo), 0x1p-32, c.bc.h64);
                             width = tb.y;
-                            const real xi = fma(dl, tb.y, tb.x);
-                            ui = xi - c.p1[i];
-                            if constexpr (KIND == BIMODAL) ubi = xi - c.p2[i];
-                            if constexpr (KIND == GENZ_DISC || KIND == GENZ_PEAK) ui = xi - c.p2[i];
+                            ui = fma(dl, tb.y, tb.x);
+                            if constexpr (KIND == BIMODAL) ubi = ui - c.p2[i];  // p2 = muB - muA
                         } else if constexpr (KIND == BIMODAL) {
                             dl = float(lo);
                             width = tb.z;

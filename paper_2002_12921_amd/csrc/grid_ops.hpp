@@ -28,7 +28,8 @@ __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2
 }
 
 // Grid tables of dimension i from its edges E[0..N] (any address space).
-//   FP64: (E_b, E_{b+1} - E_b)
+//   FP64: (E_b - cA, E_{b+1} - E_b), cA the integrand's centre (0 for user
+//         integrands); the event kernel forms x - cA with one fma
 //   FP32: with W = RN32(E_{b+1} - E_b), S = 2^(ws + 32) and g = E_b + h W / 2^32
 //         (h = 1/2 for odd N, else 0),
 //         (RN32((g - cA) S), [RN32((g - cB) S),] W 2^ws)
@@ -41,7 +42,7 @@ __device__ __forceinline__ void write_table_entry(int i, int b, double lo, doubl
     const double S = sw * 0x1p32;
     const double h = (N & 1) ? 0x1p-33 : 0.0;     // h / 2^32
     const double w = hi - lo;
-    tab64[size_t(i) * N + b] = make_double2(lo, w);
+    tab64[size_t(i) * N + b] = make_double2(lo - cA, w);
     const double W = double(float(w));
     const double g = lo + h * W;
     const float Ws = float(W * sw);

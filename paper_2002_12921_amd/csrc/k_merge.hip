@@ -62,7 +62,10 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
         c->ka32 = float(1.0 / (a * a));
         for (int i = 0; i < d; ++i) {
             c->p1_64[i] = c->cA64[i] = q[1 + i];
-            if (kind == BIMODAL) c->p2_64[i] = c->cB64[i] = q[1 + d + i];
+            if (kind == BIMODAL) {
+                c->cB64[i] = q[1 + d + i];
+                c->p2_64[i] = q[1 + d + i] - q[1 + i];  // FP64 map: u_B = u_A - (muB - muA)
+            }
         }
     } else if (kind == GENZ_DISC) {
         // nu exp(sum c x) = [nu e^{sum c a}] exp(sum c (x - a)); per dimension

@@ -39,7 +39,8 @@ __device__ __forceinline__ BinConsts bin_consts(int N)
 
 // Point, bins and width product of one event.  Dimension i takes word i mod 4
 // of the Philox block of group i div 4; delta = (lo + h)/2^32 is exact, and
-// x_i = fma(delta, W_b, E_b) as in the built-in FP64 path.
+// x_i = fma(delta, W_b, E_b), the built-in FP64 map with centre 0 (the table of
+// a user context holds E_b itself).
 struct Event {
     int b[D];
     double del[D];

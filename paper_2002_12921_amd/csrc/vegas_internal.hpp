@@ -55,7 +55,7 @@ struct DevConst {
     float ka32;      // GAUSS: RN32(1/a^2) (adjoint)
     float pad0;
     double p1_64[kMaxDim];  // GAUSS mu | BIMODAL muA | DISC c | PEAK c^2
-    double p2_64[kMaxDim];  //          | BIMODAL muB | DISC a | PEAK a
+    double p2_64[kMaxDim];  //          | BIMODAL muB - muA | DISC a | PEAK a
     float p1_32[kMaxDim];   // PEAK c^2
     float p2_32[kMaxDim];   // (unused)
     double cA64[kMaxDim];   // table centres: GAUSS mu | BIMODAL muA | DISC, PEAK a
