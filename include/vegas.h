@@ -166,7 +166,12 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, char* log, size
  * (vegas_last_iteration_device) then reads zero and vegas_refine has nothing
  * to refine from.  EINVAL otherwise. 
  * At CHUNK_END: I_t = S1/M, var_t = (S2/M - I_t^2)/(M-1) over the M events
- * of the iteration (M >= 2), the iteration is recorded and t advances. */
+ * of the iteration (M >= 2), the iteration is recorded and t advances.
+ * The call only enqueues kernel launches (no copies, no memsets, no host
+ * waits unless timing is enabled), so it can be recorded by stream capture
+ * into a HIP graph.  Its host-side bookkeeping (t, the record index) advances
+ * when the call is made, i.e. at capture time: a replayed graph re-runs the
+ * recorded iterations with their recorded t and record slots. */
 vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,
                            vegas_stream_t stream);
 
