@@ -10,7 +10,7 @@ of the FP32-mixed path; the FP64 path is timed the same way beside it.
 Also reported: the event kernel's roofline (VALU issue bound), the whole
 5 adaptation + 5 accumulation schedule for both precisions, plain Monte
 Carlo iterations (uniform grid, no histograms, no refinement), the same
-Gaussian as a user integrand compiled at run time (FP64), the Genz
+Gaussian as a user integrand compiled at run time (both precisions), the Genz
 discontinuous and product-peak integrands at d = 16, and the CPU
 oracle timed on a bounded sample of the same workload.
 
@@ -129,7 +129,7 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     microseconds each).  Then the event kernel alone: `steps` launches back
     to back between two events on its stream, whose duration per launch sets
     the roofline figure.  source: the same Gaussian as a user integrand
-    (compiled at run time; FP64), timed the same way."""
+    (compiled at run time, in the given precision), timed the same way."""
     import torch
     from paper_2002_12921_amd import Vegas
 
@@ -138,7 +138,7 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     if source is None:
         v = Vegas(D, NBINS, "gauss", params, precision, seed=0, alpha=ALPHA)
     else:
-        v = Vegas(D, NBINS, params=params, source=source, seed=0, alpha=ALPHA)
+        v = Vegas(D, NBINS, params=params, source=source, precision=precision, seed=0, alpha=ALPHA)
     init_s = time.perf_counter() - t_init
     if blocks:
         v.set_launch(blocks)
@@ -514,7 +514,8 @@ def main():
     user = None
     if not args.mixed_only:
         from paper_2002_12921_amd import user_integrands
-        user = time_path("fp64", args.steps, args.warmup, source=user_integrands.GAUSSIAN)
+        user = {p: time_path(p, args.steps, args.warmup, source=user_integrands.GAUSSIAN)
+                for p in ("fp64", "fp32_mixed")}
 
     slots = alg_slots_per_event(D)
     t_k = mixed["event_kernel_ms"] * 1e-3
@@ -573,11 +574,13 @@ def main():
     if genz is not None:
         out["genz_d16"] = genz
     if user is not None:
-        out["user_integrand_gauss_d8_fp64"] = {
-            "value": user["events_per_s"], "ms_per_step": user["ms_per_step"],
-            "event_kernel_ms": user["event_kernel_ms"], "launch": user["launch"],
-            "compile_and_init_s": user["init_s"],
-            "over_builtin_fp64": user["events_per_s"] / fp64["events_per_s"] if fp64 else None}
+        for p, builtin in (("fp64", fp64), ("fp32_mixed", mixed)):
+            u = user[p]
+            out["user_integrand_gauss_d8_" + p] = {
+                "value": u["events_per_s"], "ms_per_step": u["ms_per_step"],
+                "event_kernel_ms": u["event_kernel_ms"], "launch": u["launch"],
+                "compile_and_init_s": u["init_s"],
+                "over_builtin": u["events_per_s"] / builtin["events_per_s"] if builtin else None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]

@@ -67,8 +67,7 @@ typedef enum {
  *                  params = c[0..d-1], a[0..d-1]                       (2d)
  * For the Genz forms nu makes the integral over [0,1]^d one (sec. 3.1).
  *  VEGAS_USER      f given as device source code (see vegas_init_user); params
- *                  is the caller's array of 0..129 values, handed to f as is;
- *                  VEGAS_FP64 only. */
+ *                  is the caller's array of 0..129 values, handed to f as is. */
 enum { VEGAS_GAUSS = 0, VEGAS_BIMODAL = 1, VEGAS_GENZ_DISC = 2, VEGAS_GENZ_PEAK = 3, VEGAS_USER = 4 };
 
 /* Precision of the map and integrand.  Sums, histograms, statistics and the
@@ -121,24 +120,27 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
  * code outside the framework (sec. 2.3), here as device source compiled at run
  * time for gfx950 with hipRTC.  `source` is HIP device code that defines
  *
- *   __device__ double vegas_integrand(const double* x, int dim, const double* params);
+ *   __device__ vegas_real vegas_integrand(const vegas_real* x, int dim, const double* params);
  *
- * returning f(x) at the point x[0..dim-1] in [0,1)^dim; params points to the
- * context's n_params FP64 values in device memory (vegas_desc.params, or
- * those of vegas_set_params_device).  The macro VEGAS_DIM (= dim) is defined
- * before the source, and the HIP device math library is available.  The
+ * returning f(x) at the point x[0..dim-1] in [0,1)^dim, where vegas_real is
+ * double in a VEGAS_FP64 context and float in a VEGAS_FP32_MIXED one (the map
+ * and f in FP32, the sums and histograms in FP64, as for the built-in
+ * integrands); params points to the context's n_params FP64 values in device
+ * memory (vegas_desc.params, or those of vegas_set_params_device).  The macro
+ * VEGAS_DIM (= dim) is defined before the source, and VEGAS_FP32 in an
+ * FP32-mixed context; the HIP device math library is available.  The
  * source may define other __device__ functions and constants; it must not
  * write memory it does not own, and the names vegas_user_* and namespace
  * vegas are reserved.  Everything else of an iteration (points, map,
  * Jacobian, sums, histograms, refinement, combination) is the library's FP64
- * path, so a user integrand equal to a built-in one gives its results up to
- * rounding.
+ * path in the context's precision, so a user integrand equal to a built-in
+ * one gives its results up to rounding.
  *
- * vegas_init_user: as vegas_init_grid for desc->integrand == VEGAS_USER and
- * desc->precision == VEGAS_FP64 (else EINVAL / EUNSUPPORTED); 0 <= n_params <=
- * 129 (params may be NULL when 0).  Compiles the source for desc->dim (about
- * a second; code objects are kept per (dim, source) for the process) and
- * loads it on the current device.  VEGAS_ECOMPILE if it does not compile,
+ * vegas_init_user: as vegas_init_grid for desc->integrand == VEGAS_USER (else
+ * EINVAL); 0 <= n_params <= 129 (params may be NULL when 0).  Compiles the
+ * source for desc->dim and desc->precision (about a second; code objects are
+ * kept per (dim, precision, source) for the process) and loads it on the
+ * current device.  VEGAS_ECOMPILE if it does not compile,
  * with the compiler's messages in vegas_last_error() (lines of the source are
  * numbered from 1 in file "integrand").  Unsupported on a user context:
  * vegas_adjoint (EUNSUPPORTED) and batches.  vegas_init_grid refuses
@@ -146,11 +148,11 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
 vegas_status vegas_init_user(vegas_ctx** out, const vegas_desc* desc, const char* source, void* dev_ws,
                              size_t ws_bytes, vegas_stream_t stream);
 
-/* Compile `source` for dimension dim (1..64) as vegas_init_user would, without
- * a device: VEGAS_OK or VEGAS_ECOMPILE.  When log is not NULL the compiler's
- * messages (warnings too) are copied there, NUL-terminated and cut to
- * log_bytes. */
-vegas_status vegas_user_compile(const char* source, int32_t dim, char* log, size_t log_bytes);
+/* Compile `source` for dimension dim (1..64) and precision (VEGAS_FP64 or
+ * VEGAS_FP32_MIXED) as vegas_init_user would, without a device: VEGAS_OK or
+ * VEGAS_ECOMPILE.  When log is not NULL the compiler's messages (warnings too)
+ * are copied there, NUL-terminated and cut to log_bytes. */
+vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precision, char* log, size_t log_bytes);
 
 /* Run n_events events (1 <= n_events <= 2^40) of the current iteration t.
  * Event e draws, for each group j of four dimensions,

@@ -79,7 +79,7 @@ def lib() -> ctypes.CDLL:
         "vegas_workspace_size": [P(Desc), P(sz)],
         "vegas_init_grid": [P(vp), P(Desc), vp, sz, vp],
         "vegas_init_user": [P(vp), P(Desc), ctypes.c_char_p, vp, sz, vp],
-        "vegas_user_compile": [ctypes.c_char_p, i32, ctypes.c_char_p, sz],
+        "vegas_user_compile": [ctypes.c_char_p, i32, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],
         "vegas_refine": [vp, vp],
         "vegas_result": [vp, P(Result), vp],

@@ -72,11 +72,10 @@ vegas_status check_desc(const vegas_desc* d)
     if (!(d->alpha >= 0.0) || !std::isfinite(d->alpha)) return fail(VEGAS_EINVAL, "alpha must be finite and >= 0");
     if (d->problem < 0 || d->problem >= (1 << 24)) return fail(VEGAS_EINVAL, "problem must be in [0, 2^24)");
     if (d->integrand == VEGAS_USER) {
-        if (d->precision != VEGAS_FP64) return fail(VEGAS_EUNSUPPORTED, "user integrands run in VEGAS_FP64 only");
         if (d->n_params < 0 || d->n_params > kMaxParams)
             return fail(VEGAS_EINVAL, "a user integrand takes 0..%d params (got %d)", kMaxParams, d->n_params);
         if (d->n_params > 0 && !d->params) return fail(VEGAS_EINVAL, "params is NULL");
-        const size_t lds = lds_bytes(FP64, USER, d->dim, d->n_bins) + 128;
+        const size_t lds = lds_bytes(d->precision == VEGAS_FP64 ? FP64 : FP32, USER, d->dim, d->n_bins) + 128;
         if (lds > kLdsLimit)
             return fail(VEGAS_EUNSUPPORTED, "dim*n_bins too large: %zu bytes of LDS per block (limit %zu)", lds, kLdsLimit);
         return VEGAS_OK;
@@ -161,14 +160,14 @@ int sample_blocks(const vegas_ctx* c, int64_t n)
 }
 
 // LDS of the runtime-compiled event kernel: table, histogram replicas, wave partials.
-size_t user_lds(int d, int N, int rep, bool hist)
+size_t user_lds(int prec, int d, int N, int rep, bool hist)
 {
-    return lds_bytes(FP64, USER, d, N, hist ? rep : 0) + sizeof(double) * (kBlock / 64);
+    return lds_bytes(prec, USER, d, N, hist ? rep : 0) + sizeof(double) * (kBlock / 64);
 }
 
 size_t event_lds(const vegas_ctx* c, int rep, bool hist)
 {
-    return c->kind == USER ? user_lds(c->d, c->N, rep, hist) : sample_lds(c->prec, c->kind, c->d, c->N, rep, hist);
+    return c->kind == USER ? user_lds(c->prec, c->d, c->N, rep, hist) : sample_lds(c->prec, c->kind, c->d, c->N, rep, hist);
 }
 
 SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
@@ -311,7 +310,7 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
         return bail(fail(VEGAS_EHIP, "device query: %s", hipGetErrorString(he)));
     if (source) {
         std::string code, log;
-        st = rtc_compile(source, c->d, code, log);
+        st = rtc_compile(source, c->d, c->prec, code, log);
         if (st != VEGAS_OK) return bail(st);
         if ((he = hipModuleLoadData(&c->umod, code.data())) != hipSuccess) {
             c->umod = nullptr;
@@ -397,12 +396,14 @@ vegas_status vegas_init_user(vegas_ctx** out, const vegas_desc* desc, const char
     return init_ctx(out, desc, source, dev_ws, ws_bytes, stream);
 }
 
-vegas_status vegas_user_compile(const char* source, int32_t dim, char* log, size_t log_bytes)
+vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precision, char* log, size_t log_bytes)
 {
     if (!source) return fail(VEGAS_EINVAL, "source is NULL");
     if (dim < 1 || dim > kMaxDim) return fail(VEGAS_EINVAL, "dim must be in [1, %d] (got %d)", kMaxDim, dim);
+    if (precision != VEGAS_FP64 && precision != VEGAS_FP32_MIXED)
+        return fail(VEGAS_EINVAL, "unknown precision %d", precision);
     std::string code, msg;
-    const vegas_status st = rtc_compile(source, dim, code, msg);
+    const vegas_status st = rtc_compile(source, dim, precision == VEGAS_FP64 ? FP64 : FP32, code, msg);
     if (log && log_bytes > 0) {
         const size_t n = std::min(msg.size(), log_bytes - 1);
         std::memcpy(log, msg.data(), n);
@@ -597,13 +598,13 @@ vegas_status vegas_dump_events(vegas_ctx* c, int64_t iteration, int64_t first, i
     a.d = c->d;
     a.N = c->N;
     if (c->kind == USER) {
-        // one event per thread, 256 threads, the FP64 table in LDS
+        // one event per thread, 256 threads, the table in LDS
         const uint64_t blocks = std::min<uint64_t>((a.n + 255) / 256, 4096);
         const double* params = c->P.params;
         void* args[] = {&a, const_cast<double**>(&params)};
         VEGAS_HIP(hipModuleLaunchKernel(c->udump, unsigned(blocks), 1, 1, 256, 1, 1,
-                                        unsigned(sizeof(double2) * c->d * c->N), static_cast<hipStream_t>(stream), args,
-                                        nullptr));
+                                        unsigned(tab_entry_bytes(c->prec, USER) * c->d * c->N),
+                                        static_cast<hipStream_t>(stream), args, nullptr));
         return VEGAS_OK;
     }
     VEGAS_HIP(launch_dump(c->prec, c->kind, a, static_cast<hipStream_t>(stream)));

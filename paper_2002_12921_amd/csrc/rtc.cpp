@@ -19,7 +19,7 @@ namespace vegas {
 namespace {
 
 std::mutex g_cache_mu;
-std::map<std::pair<int, std::string>, std::string> g_cache;
+std::map<std::pair<int, std::string>, std::string> g_cache;  // key: (d + 1000 * prec, source)
 constexpr size_t kCacheEntries = 64;
 
 std::string program_log(hiprtcProgram p)
@@ -34,12 +34,13 @@ std::string program_log(hiprtcProgram p)
 
 }  // namespace
 
-vegas_status rtc_compile(const char* source, int d, std::string& code, std::string& log)
+vegas_status rtc_compile(const char* source, int d, int prec, std::string& code, std::string& log)
 {
     code.clear();
     log.clear();
     if (!source) return fail(VEGAS_EINVAL, "source is NULL");
-    const auto key = std::make_pair(d, std::string(source));
+    const bool fp32 = prec != 0;
+    const auto key = std::make_pair(d + (fp32 ? 1000 : 0), std::string(source));
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
         auto it = g_cache.find(key);
@@ -50,7 +51,8 @@ vegas_status rtc_compile(const char* source, int d, std::string& code, std::stri
     }
     // the caller's lines are numbered from 1 in file "integrand" in messages
     const std::string text = "#define VEGAS_DIM " + std::to_string(d) + "\n#define VEGAS_THREADS " +
-                             std::to_string(kUserThreads) +
+                             std::to_string(kUserThreads) + (fp32 ? "\n#define VEGAS_FP32 1\ntypedef float vegas_real;"
+                                                                  : "\ntypedef double vegas_real;") +
                              "\n#include \"device_common.hpp\"\n#line 1 \"integrand\"\n" + source +
                              "\n#include \"k_user_rtc.hpp\"\n";
     const char* headers[] = {kRtcInternal, kRtcCommon, kRtcUser};

@@ -11,9 +11,10 @@ namespace vegas {
 constexpr int kUserThreads = 512;
 
 // Compiles the user-integrand kernels (k_user_rtc.hpp after `source`) for
-// dimension d and gfx950 with the runtime compiler; no device is needed.  On
-// VEGAS_OK `code` holds the code object; `log` always holds the compiler's
-// messages.  Compiled code objects are kept per (d, source) for the process.
-vegas_status rtc_compile(const char* source, int d, std::string& code, std::string& log);
+// dimension d, precision prec (FP64 or FP32) and gfx950 with the runtime
+// compiler; no device is needed.  On VEGAS_OK `code` holds the code object;
+// `log` always holds the compiler's messages.  Compiled code objects are kept
+// per (d, precision, source) for the process.
+vegas_status rtc_compile(const char* source, int d, int prec, std::string& code, std::string& log);
 
 }  // namespace vegas

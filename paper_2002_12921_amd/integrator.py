@@ -35,11 +35,12 @@ def make_desc(dim: int, n_bins: int, integrand, params: Sequence[float], precisi
     return d, p
 
 
-def compile_user(source: str, dim: int) -> tuple[bool, str]:
-    """Compile a user integrand for dimension dim without a device (see
-    vegas_user_compile): (compiled?, compiler messages)."""
+def compile_user(source: str, dim: int, precision="fp64") -> tuple[bool, str]:
+    """Compile a user integrand for dimension dim and a precision without a
+    device (see vegas_user_compile): (compiled?, compiler messages)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     buf = ctypes.create_string_buffer(1 << 16)
-    st = lib().vegas_user_compile(source.encode(), int(dim), buf, len(buf))
+    st = lib().vegas_user_compile(source.encode(), int(dim), prec, buf, len(buf))
     if st not in (_lib.VEGAS_OK, _lib.VEGAS_ECOMPILE):
         check(st, "user_compile")
     return st == _lib.VEGAS_OK, buf.value.decode(errors="replace")
@@ -49,9 +50,10 @@ class Vegas:
     """One adaptive Vegas integration on the current HIP device.
 
     source: HIP device code defining
-    ``__device__ double vegas_integrand(const double* x, int dim, const double* params)``
-    (a user integrand, compiled at run time; integrand and precision then
-    default to "user" and "fp64", and params to none)."""
+    ``__device__ vegas_real vegas_integrand(const vegas_real* x, int dim, const double* params)``
+    (a user integrand, compiled at run time; vegas_real is double for
+    precision "fp64" and float for "fp32_mixed"; integrand then defaults to
+    "user" and params to none)."""
 
     def __init__(self, dim: int, n_bins: int = 50, integrand=None,
                  params: Optional[Sequence[float]] = None, precision="fp64", seed: int = 0,

@@ -128,12 +128,22 @@ def test_user_compile_on_host():
     assert not ok and "integrand:3:" in log and "error" in log
     ok, log = compile_user("__device__ double not_the_entry(const double* x) { return 1.0; }\n", 2)
     assert not ok and "vegas_integrand" in log
+    # FP32-mixed contexts hand f float coordinates: a source written for
+    # vegas_real compiles in both precisions, one written for double* does not
+    from paper_2002_12921_amd import user_integrands as ui
+    for src in (ui.GAUSSIAN, ui.OSCILLATORY, ui.SINE_PRODUCT):
+        for prec in ("fp64", "fp32_mixed"):
+            ok, log = compile_user(src, 5, prec)
+            assert ok, (prec, log)
+    ok, log = compile_user(GOOD_SRC, 5, "fp32_mixed")
+    assert not ok and "error" in log
     L = _lib.lib()
-    assert L.vegas_user_compile(None, 3, None, 0) == _lib.VEGAS_EINVAL
-    assert L.vegas_user_compile(GOOD_SRC.encode(), 0, None, 0) == _lib.VEGAS_EINVAL
-    assert L.vegas_user_compile(GOOD_SRC.encode(), 65, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(None, 3, 0, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(GOOD_SRC.encode(), 0, 0, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(GOOD_SRC.encode(), 65, 0, None, 0) == _lib.VEGAS_EINVAL
+    assert L.vegas_user_compile(GOOD_SRC.encode(), 3, 7, None, 0) == _lib.VEGAS_EINVAL
     buf = ctypes.create_string_buffer(8)  # the log is cut to the buffer, NUL-terminated
-    assert L.vegas_user_compile(b"garbage(", 2, buf, 8) == _lib.VEGAS_ECOMPILE
+    assert L.vegas_user_compile(b"garbage(", 2, 0, buf, 8) == _lib.VEGAS_ECOMPILE
     assert len(buf.value) <= 7
 
 
@@ -147,7 +157,7 @@ def test_user_desc_checks():
     d, keep = make_desc(5, 40, "user", [1.0] * 130, "fp64")
     assert _size(d)[0] == _lib.VEGAS_EINVAL
     d, keep = make_desc(5, 40, "user", [], "fp32_mixed")
-    assert _size(d)[0] == _lib.VEGAS_EUNSUPPORTED
+    assert _size(d)[0] == _lib.VEGAS_OK
     ctx = ctypes.c_void_p()
     u, keep = make_desc(5, 40, "user", [], "fp64")
     g, keep2 = make_desc(4, 50, "gauss", [0.1] + [0.5] * 4)

@@ -1,10 +1,15 @@
 """GPU parity of user integrands (device source compiled at run time).
 
-The runtime-compiled event kernel is the FP64 path with the caller's f, so
-the bar is the FP64 one: sums S1, S2 within 1e-12 relative, histograms within
-1e-12 of each dimension's total, refinement within 1e-12 absolute, against
-the oracle's points and weights (oracle.accumulate_fn) with f written in NumPy
-(or, for the Gaussian, the oracle's own integrand).
+The runtime-compiled event kernel is the built-in path of the context's
+precision with the caller's f, so the bars are the built-in ones: FP64 sums
+S1, S2 within 1e-12 relative, histograms within 1e-12 of each dimension's
+total, refinement within 1e-12 absolute.  In an FP32-mixed context the
+caller's f sees FP32 coordinates with no centre offset, so its error depends
+on f's slope: the FP32 tests sum a per-event bound derived from the FP32 map
+and f's sensitivity over the oracle's events and check the library inside
+it (and the bound far below the sums).  The reference is the oracle's points and weights
+(oracle.accumulate_fn) with f written in NumPy (or, for the Gaussian, the
+oracle's own integrand).
 """
 import numpy as np
 import pytest
@@ -197,8 +202,9 @@ def test_user_errors_and_nonfinite():
         Vegas(d, 10, source="__device__ double vegas_integrand(const double* x, int d, const double* p) { return y; }")
     with pytest.raises(VegasError, match="ECOMPILE"):
         Vegas(d, 10, source="__device__ double some_other_name(const double* x) { return 1.0; }")
-    with pytest.raises(VegasError, match="EUNSUPPORTED"):
-        Vegas(d, 10, source=ui.SINE_PRODUCT, precision="fp32_mixed")
+    with pytest.raises(VegasError, match="ECOMPILE"):  # FP32 contexts hand f float coordinates
+        Vegas(d, 10, precision="fp32_mixed",
+              source="__device__ double vegas_integrand(const double* x, int d, const double* p) { return x[0]; }")
     with pytest.raises(VegasError, match="EINVAL"):
         Vegas(d, 10, integrand="user", params=[])  # a user kind needs a source
     v = Vegas(d, 10, source=ui.SINE_PRODUCT)
@@ -244,3 +250,119 @@ def test_user_oscillatory_closed_form():
     r = v.result()
     exact = _osc_exact(params)
     assert abs(r["integral"] - exact) < 5 * r["sigma"], (r["integral"], exact, r["sigma"])
+
+
+def _x_err32(E, x):
+    """Bound on |x_kernel - x| for the FP32 map of a user context (centre 0):
+    2^-24 (3 W + 2 x), 0.1% margin, W the width of x's bin (the largest of it
+    and its neighbours', for points that round onto an edge)."""
+    d, N = E.shape[0], E.shape[1] - 1
+    out = np.empty_like(x)
+    for i in range(d):
+        W = np.diff(E[i])
+        b = np.clip(np.searchsorted(E[i], x[:, i], side="right") - 1, 0, N - 1)
+        Wm = np.maximum(W[b], np.maximum(W[np.maximum(b - 1, 0)], W[np.minimum(b + 1, N - 1)]))
+        out[:, i] = 2.0 ** -24 * (3 * Wm + 2 * x[:, i]) * 1.001
+    return out
+
+
+def _check_fp32_sums(got, ref, bnd1, bnd2, tag):
+    """got = (S1, S2, H) of the library; ref = the oracle's (S1, S2, H, sum |v|);
+    bnd1 = sum of |dv| bounds, bnd2 = (S2-like, H-like) of |d(v^2)| bounds,
+    all from accumulate_fn; plus FP64 summation slack."""
+    S1, S2, H = got
+    o1, o2, Ho, oa = ref
+    b2, Hb = bnd2
+    assert abs(S1 - o1) <= bnd1 + TOL * oa, (tag, S1, o1, bnd1)
+    assert abs(S2 - o2) <= b2 + TOL * o2, (tag, S2, o2, b2)
+    assert np.all(np.abs(H - Ho) <= Hb + TOL * Ho.sum(axis=1, keepdims=True)), tag
+    # the bounds have teeth: far below the sums themselves
+    assert bnd1 <= 1e-4 * oa and b2 <= 1e-4 * o2, (tag, bnd1 / oa, b2 / o2)
+
+
+@pytest.mark.parametrize("N", [50, 37])
+def test_user_fp32_gaussian_matches_oracle(N):
+    """FP32-mixed user context (map and the caller's f at FP32 coordinates,
+    sums and histograms in FP64): the Gaussian as user source against the
+    oracle's FP64 Gaussian, per iteration.  An arbitrary f has no centre to
+    offset the table from, so x carries the FP32 map's error 2^-24 (3 W + 2 x)
+    and each v = f w is off by at most r |v|, r = expm1(sum (2 |x_i - mu_i| +
+    e_i) e_i / a^2) + 2^-24 (2 d + 6) (the exponent's sensitivity, f's
+    rounding to FP32, the FP32 width product); the oracle sums those bounds
+    over its own events and the library must land inside them.  Refinement
+    against the oracle's refinement of the library's histograms."""
+    d, M = 8, 200_003
+    a, mu = 0.1, np.linspace(0.35, 0.65, d)
+    params = [a] + list(mu)
+    u = Vegas(d, N, params=params, source=ui.GAUSSIAN, precision="fp32_mixed", seed=9)
+    pr = oracle.Problem(d, N, oracle.GAUSS, params, seed=9)
+    f = lambda x: (a * np.sqrt(np.pi)) ** -d * np.exp(-np.sum((x - mu) ** 2, axis=1) / a**2)
+
+    for t in range(3):
+        E = u.edges()
+
+        def r(x):
+            e = _x_err32(E, x)
+            return np.expm1(np.sum((2 * np.abs(x - mu) + e) * e, axis=1) / a**2) * 1.001 \
+                + 2.0 ** -24 * (2 * d + 6)
+
+        u.iterate(M)
+        got = u.last_iteration()
+        o1, o2, Ho = oracle.accumulate(pr, E, t, M)
+        _, _, _, b1 = oracle.accumulate_fn(d, N, 9, 0, E, t, M, lambda x: f(x) * r(x), with_abs=True)
+        _, b2, Hb = oracle.accumulate_fn(d, N, 9, 0, E, t, M, lambda x: f(x) * np.sqrt(2 * r(x) + r(x) ** 2))
+        _check_fp32_sums(got, (o1, o2, Ho, abs(o1)), b1, (b2, Hb), t)
+        u.refine()
+        assert np.max(np.abs(u.edges() - oracle.refine(got[2], E, 1.5))) <= 1e-12
+
+
+@pytest.mark.parametrize("d,N,M", [(5, 37, 100_003), (13, 64, 60_001), (20, 20, 50_000)])
+def test_user_fp32_oscillatory_lockstep(d, N, M):
+    """FP32-mixed user context on a non-built-in integrand, against
+    oracle.accumulate_fn through three refinements (d = 20 moves the width
+    product's exponent out twice).  cos has slope at most 1, so |dv| <= w e
+    with e = sum |c_i| e_i + 2^-24 (2 d + 6) |f| + 1e-14 (the FP32 map's x
+    error e_i, f's and the width product's FP32 rounding, FP64 evaluation);
+    the oracle sums those bounds over its events."""
+    params = [0.1] + list(np.linspace(0.5, 2.5, d))
+    c = np.abs(np.asarray(params[1:]))
+    f = _osc_np(params)
+    v = Vegas(d, N, params=params, source=ui.OSCILLATORY, precision="fp32_mixed", seed=77, problem=5)
+    for t in range(3):
+        E = v.edges()
+
+        def e(x):
+            return _x_err32(E, x) @ c * 1.001 + 2.0 ** -24 * (2 * d + 6) * np.abs(f(x)) + 1e-14
+
+        v.iterate(M)
+        got = v.last_iteration()
+        ref = oracle.accumulate_fn(d, N, 77, 5, E, t, M, f, with_abs=True)
+        b1, _, _ = oracle.accumulate_fn(d, N, 77, 5, E, t, M, e)
+        _, b2, Hb = oracle.accumulate_fn(d, N, 77, 5, E, t, M,
+                                         lambda x: np.sqrt(2 * np.abs(f(x)) * e(x) + e(x) ** 2))
+        _check_fp32_sums(got, ref, b1, (b2, Hb), t)
+        v.refine()
+
+
+def test_user_fp32_dump_events():
+    """Per-event records of an FP32-mixed user context: bins exact; delta is
+    RN32 of the exact delta (even N); x within 2^-24 (3 w + 2 x) of the
+    oracle's; w within 2^-24 (2d + 4); f is the source's FP64 value at the
+    kernel's x, rounded once to FP32."""
+    d, N = 6, 40
+    params = [0.3] + list(np.linspace(1.0, 3.0, d))
+    v = Vegas(d, N, params=params, source=ui.OSCILLATORY, precision="fp32_mixed", seed=3)
+    pr = oracle.Problem(d, N, oracle.GAUSS, [0.1] + [0.5] * d, seed=3)
+    E = oracle.run(pr, oracle.uniform_edges(d, N), 2, 20000, [1, 1], [1, 1])["edges"]
+    v.set_edges(E)
+    got = v.dump_events(500, 5000 + 13, iteration=4).cpu().numpy()
+    ref = oracle.events(pr, E, 4, 500, 5000 + 13)
+    assert np.array_equal(got[:, :d], ref[:, :d])
+    assert np.array_equal(got[:, d:2 * d], ref[:, d:2 * d].astype(np.float32).astype(np.float64))
+    bi = ref[:, :d].astype(np.int64)
+    wid = np.stack([np.diff(E[i])[bi[:, i]] for i in range(d)], axis=1)
+    xg, xo = got[:, 2 * d:3 * d], ref[:, 2 * d:3 * d]
+    assert np.all(np.abs(xg - xo) <= 2.0 ** -24 * (3 * wid + 2 * np.abs(xo)) * 1.001)
+    assert np.max(np.abs(got[:, 3 * d] - ref[:, 3 * d]) / ref[:, 3 * d]) <= 2.0 ** -24 * (2 * d + 4)
+    fx = _osc_np(params)(xg.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(got[:, 3 * d + 1] - fx) <= 2.0 ** -24 * np.abs(fx) + 1e-15)
