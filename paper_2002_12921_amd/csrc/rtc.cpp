@@ -12,6 +12,7 @@
 #include <utility>
 
 #include "capi_util.hpp"
+#include "vegas_internal.hpp"
 #include "vegas_rtc_sources.inc"  // kRtcInternal, kRtcCommon, kRtcUser (written by build.py)
 
 namespace vegas {
@@ -39,7 +40,7 @@ vegas_status rtc_compile(const char* source, int d, int prec, std::string& code,
     code.clear();
     log.clear();
     if (!source) return fail(VEGAS_EINVAL, "source is NULL");
-    const bool fp32 = prec != 0;
+    const bool fp32 = prec == FP32;
     const auto key = std::make_pair(d + (fp32 ? 1000 : 0), std::string(source));
     {
         std::lock_guard<std::mutex> g(g_cache_mu);
