@@ -28,7 +28,9 @@ class VegasIntegral(torch.autograd.Function):
                             mu.detach().reshape(-1).to(torch.float64)]).contiguous()
         vegas.set_params_device(params)
         t = vegas.iteration_index
-        vegas.iterate(n_events, refine=False, combine=False)
+        # frozen grid: no histograms (the sums are bitwise those of the
+        # histogram variant)
+        vegas.iterate(n_events, refine=False, combine=False, hist=False)
         out = torch.empty(2, dtype=torch.float64, device=mu.device)
         vegas.last_iteration_device(out)
         ctx.vegas, ctx.t, ctx.n = vegas, t, n_events

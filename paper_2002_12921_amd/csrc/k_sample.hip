@@ -190,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
 // v * d ln f / d theta_j, theta = (mu_0..mu_{d-1}, a):
 //   d ln f / d mu_j = 2 (x_j - mu_j) / a^2,  d ln f / d a = (2 s / a^2 - d) / a.
 // Block rows go to a partial table; k_adjoint_merge adds them in a fixed
-// order and writes gout * sum / M.
-template <class P, int DMAX>
+// order and writes gout * sum / M.  EXACT: d == DMAX, so the per-dimension
+// guards fold away and the table reads of an event can all be in flight.
+template <class P, int DMAX, bool EXACT>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 {
     using tab_t = typename TabEntry<P, GAUSS>::type;
@@ -211,7 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     // the FP32 path's u carries the factor S = 2^(ws + 32): its constants take S^-1, S^-2 (exact)
     const double ds = P::is64 ? 1.0 : double(c->dscale32) * 0x1p-32;
     const real ka = P::is64 ? real(c->kexp64) : real(double(c->ka32) * ds);
+    // 2 u ka rounds to the same value as u (2 ka): the factor 2 is exact
+    const real ka2 = real(2) * ka;
     const double inv_a = c->inv_a;
+    const int d = EXACT ? DMAX : a.d;
     const double ka64 = c->kexp64 * ds * ds;
     double g[DMAX + 1];
 #pragma unroll
@@ -219,26 +223,26 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
-        EventEval<P, GAUSS, DMAX> ev;
-        ev.run(cst, tab, k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
+        EventEval<P, GAUSS, DMAX, EXACT> ev;
+        ev.run(cst, tab, k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
         const double v = ev.value(cst);
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
-            if (j < a.d) {
-                const real dl = real(2) * ev.u[j] * ka;
+            if (j < d) {
+                const real dl = ev.u[j] * ka2;
                 g[j] += v * double(dl);
             }
         }
-        const double da = 2.0 * ev.s64 * ka64 - double(a.d);
+        const double da = 2.0 * ev.s64 * ka64 - double(d);
         g[DMAX] += v * (da * inv_a);
     }
 
-    double* row = a.partials + size_t(blockIdx.x) * (a.d + 1);
+    double* row = a.partials + size_t(blockIdx.x) * (d + 1);
 #pragma unroll
     for (int j = 0; j <= DMAX; ++j) {
-        if (j < a.d || j == DMAX) {
+        if (j < d || j == DMAX) {
             const double t = block_sum(g[j], red);
-            if (threadIdx.x == 0) row[j < a.d ? j : a.d] = t;
+            if (threadIdx.x == 0) row[j < d ? j : d] = t;
         }
     }
 }
@@ -356,7 +360,10 @@ static const void* dump_fn_kind(int kind, int d)
 template <class P>
 static const void* adjoint_fn(int d)
 {
-    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_>))
+    if (d == dim_bucket(d)) {
+        VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_adjoint<P, D_, true>))
+    }
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_, false>))
 }
 
 size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist)

@@ -379,11 +379,14 @@ def test_nonfinite_is_reported():
         v.result()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
-def test_adjoint_matches_oracle(prec, tol):
+@pytest.mark.parametrize("d", [8, 5, 12])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_adjoint_matches_oracle(prec, d):
     """The adjoint kernel vs the oracle's per-sample analytic gradient at the
-    same points and grid; tolerance relative to the L1 size of the terms."""
-    d, N, M, t = 8, 50, 300_000, 5
+    same points and grid; tolerance (_tol) relative to the L1 size of the
+    terms (d = 8 and 12 fill their kernel's dimension bucket, d = 5 does not)."""
+    N, M, t = 50, 300_000, 5
+    tol = _tol(prec, d)
     mu = np.random.default_rng(0).uniform(0.3, 0.7, d).astype(np.float32)
     params = [0.1] + [float(m) for m in mu]
     E = _adapted_edges(d, N, params)
