@@ -132,9 +132,12 @@ vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_
  * source may define other __device__ functions and constants; it must not
  * write memory it does not own, and the names vegas_user_* and namespace
  * vegas are reserved.  Everything else of an iteration (points, map,
- * Jacobian, sums, histograms, refinement, combination) is the library's FP64
- * path in the context's precision, so a user integrand equal to a built-in
- * one gives its results up to rounding.
+ * Jacobian, sums, histograms, refinement, combination) is the library's path
+ * in the context's precision, so a user integrand equal to a built-in one
+ * gives its results up to rounding.  (In an FP32-mixed context the table has
+ * no integrand centre to be offset from: x carries the FP32 map's absolute
+ * error, at most about 2^-24 (3 W + 2 x) for a bin of width W, and f's
+ * error follows from its slope.)
  *
  * vegas_init_user: as vegas_init_grid for desc->integrand == VEGAS_USER (else
  * EINVAL); 0 <= n_params <= 129 (params may be NULL when 0).  Compiles the

@@ -23,9 +23,10 @@ class VegasIntegral(torch.autograd.Function):
         d = vegas.dim
         if mu.numel() != d or a.numel() != 1:
             raise ValueError(f"mu must have {d} elements and a one")
-        # parameter layout of the Gaussian integrand: a, mu[0..d-1]
-        params = torch.cat([a.detach().reshape(1).to(torch.float64),
-                            mu.detach().reshape(-1).to(torch.float64)]).contiguous()
+        # parameter layout of the Gaussian integrand: a, mu[0..d-1]; FP32
+        # parameters go to the library as they are (it widens them, exactly)
+        pt = torch.float32 if mu.dtype == torch.float32 and a.dtype == torch.float32 else torch.float64
+        params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)]).contiguous()
         vegas.set_params_device(params)
         t = vegas.iteration_index
         # frozen grid: no histograms (the sums are bitwise those of the

@@ -30,7 +30,7 @@ constexpr int kHistSlots = 8;
 constexpr int kMergeThreads = 1024; // threads per block of the reduction kernel
 constexpr size_t kLdsLimit = 160 * 1024;
 
-// USER: an integrand compiled at run time from the caller's source (FP64 only)
+// USER: an integrand compiled at run time from the caller's source
 enum Kind { GAUSS = 0, BIMODAL = 1, GENZ_DISC = 2, GENZ_PEAK = 3, USER = 4 };
 enum Prec { FP64 = 0, FP32 = 1 };
 

@@ -401,12 +401,15 @@ def test_adjoint_matches_oracle(prec, d):
     assert np.all(np.abs(got - want) <= tol * 2.5 * Gabs / M), (got, want)
 
 
-def test_autograd_function():
-    """VegasIntegral: forward = one frozen-grid estimate, backward = adjoint."""
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_autograd_function(dtype):
+    """VegasIntegral: forward = one frozen-grid estimate, backward = adjoint
+    (FP32 parameters reach the library as FP32, FP64 ones as FP64; both hold
+    FP32 values here, so the estimate and gradient are the same)."""
     from paper_2002_12921_amd.autograd import vegas_integral
     d, N, M = 4, 40, 200_000
-    mu = torch.tensor([0.15, 0.45, 0.5, 0.62], dtype=torch.float32, device="cuda", requires_grad=True)
-    a = torch.tensor(0.1, dtype=torch.float32, device="cuda", requires_grad=True)
+    mu = torch.tensor([0.15, 0.45, 0.5, 0.62], dtype=torch.float32, device="cuda").to(dtype).requires_grad_(True)
+    a = torch.tensor(0.1, dtype=torch.float32, device="cuda").to(dtype).requires_grad_(True)
     params = [0.1] + [0.15, 0.45, 0.5, 0.62]
     p32 = [float(np.float32(x)) for x in params]
     v = Vegas(d, N, "gauss", p32, "fp64")
