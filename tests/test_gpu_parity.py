@@ -182,6 +182,39 @@ def test_lockstep_iterations(prec, tol):
         assert np.all(np.diff(En, axis=1) > 0)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32_mixed", 1e-6), ("fp64", 1e-12)])
+def test_full_size_c2_iterations(prec, tol):
+    """The benchmarked configuration itself: the d = 8 Gaussian (a = 0.1,
+    mu = 0.5), 50 bins, seed 0, 1e7 events per iteration, with the automatic
+    launch the benchmark times (1024-thread blocks, 16 replicas: the
+    fixed-stride histogram layout) and its step (iterate with the refinement
+    fused, not combined).  Two adaptation steps from the uniform grid, each
+    against the oracle on the library's own grid: S1, S2 and every histogram
+    bin at the path's tolerance, the refined grid at 1e-12.  Then sampled
+    event records, one by one against the oracle: the first events of the
+    iteration, a middle stretch, and its last events (counters near 1e7)."""
+    d, N, M = 8, 50, 10_000_000
+    params = _gauss(d)
+    v = Vegas(d, N, "gauss", params, prec, seed=0, alpha=1.5)
+    info = v.launch_info()
+    assert info["threads"] == 1024 and info["replicas"] == 16, info
+    pr = oracle.Problem(d, N, oracle.GAUSS, params, seed=0)
+    for t in range(2):
+        E = v.edges()
+        v.iterate(M, refine=True, combine=False)
+        S1, S2, H = v.last_iteration()
+        o1, o2, Ho = oracle.accumulate(pr, E, t, M)
+        assert abs(S1 - o1) <= tol * abs(o1), (t, S1, o1)
+        assert abs(S2 - o2) <= tol * abs(o2), (t, S2, o2)
+        assert _hist_close(H, Ho, tol), t
+        assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
+    E = v.edges()
+    for first, count in ((0, 4096), (M // 2 - 2048, 4096), (M - 4096 - 13, 4096 + 13)):
+        got = v.dump_events(first, count, iteration=2).cpu().numpy()
+        ref = oracle.events(pr, E, 2, first, count)
+        _check_events(got, ref, d, prec != "fp64", "gauss", params, N, E)
+
+
 def test_free_running_fp64_c1():
     """Plain FP64 Vegas, d = 4, a = 0.1, 50 bins, 10 iterations x 1e5 events,
     alpha = 1.5, seed 0, refining after each iteration, all combined."""
