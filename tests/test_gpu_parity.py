@@ -358,6 +358,31 @@ def test_bimodal_d20_streamed(prec):
     assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_full_size_bimodal_d20_streamed(prec):
+    """The d = 20 bimodal workload at the benchmark's chunk size and launch:
+    one adaptation iteration streamed as three chunks of 1e7 events (the
+    benchmark streams ten per iteration through the same launch), refined at
+    its end, on a grid crowded at the peaks so that the sums see them;
+    against the oracle over the same 3e7 events."""
+    from paper_2002_12921_amd import workloads
+    d, N, per, chunks = 20, 100, 10_000_000, 3
+    params = workloads.bimodal20()
+    E = _two_peak_grid(d, N)
+    v = Vegas(d, N, "bimodal", params, prec, seed=0, alpha=1.5)
+    v.set_edges(E)
+    for k in range(chunks):
+        v.iterate(per, chunk="begin" if k == 0 else ("end" if k == chunks - 1 else "mid"), refine=True)
+    S1, S2, H = v.last_iteration()
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, oracle.BIMODAL, params, seed=0), E, 0, chunks * per)
+    tol = _tol(prec, 8)
+    assert o1 > 1e-3
+    assert abs(S1 - o1) <= tol * o1, (S1, o1)
+    assert abs(S2 - o2) <= tol * o2, (S2, o2)
+    assert _hist_close(H, Ho, tol)
+    assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
+
+
 def test_checkpoint_resume():
     d, N, M = 5, 30, 40_000
     params = _gauss(d, 0.12)
@@ -520,6 +545,33 @@ def test_genz_d16_lockstep(kind, prec, tol):
             assert np.any(Ho == 0.0)  # empty bins below the thresholds
         v.refine()
         assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kind", ["genz_disc", "genz_peak"])
+def test_full_size_genz_d16(kind, prec):
+    """The Genz workloads as benchmarked: d = 16, 50 bins, seed 0, 1e7 events,
+    the automatic launch (one 1024-thread block of 16 replicas per CU), one
+    adaptation step from the uniform grid against the oracle: sums and
+    histograms at the path's tolerance (1e-4 for the discontinuous one in
+    FP32-mixed, whose x_i > a_i decisions flip within FP32 rounding of a
+    threshold), the refined grid at 1e-12."""
+    from paper_2002_12921_amd import workloads
+    d, N, M = 16, 50, 10_000_000
+    params = workloads.genz16(kind)
+    kid = oracle.GENZ_DISC if kind == "genz_disc" else oracle.GENZ_PEAK
+    v = Vegas(d, N, kind, params, prec, seed=0, alpha=1.5)
+    info = v.launch_info()
+    assert info["threads"] == 1024 and info["replicas"] == 16, info
+    E = v.edges()
+    v.iterate(M, refine=True, combine=False)
+    S1, S2, H = v.last_iteration()
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, kid, params, seed=0), E, 0, M)
+    tol = 1e-12 if prec == "fp64" else (1e-4 if kind == "genz_disc" else 1e-6)
+    assert abs(S1 - o1) <= tol * abs(o1), (S1, o1)
+    assert abs(S2 - o2) <= tol * abs(o2), (S2, o2)
+    assert _hist_close(H, Ho, tol)
+    assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])

@@ -366,3 +366,21 @@ def test_user_fp32_dump_events():
     assert np.max(np.abs(got[:, 3 * d] - ref[:, 3 * d]) / ref[:, 3 * d]) <= 2.0 ** -24 * (2 * d + 4)
     fx = _osc_np(params)(xg.astype(np.float32).astype(np.float64))
     assert np.all(np.abs(got[:, 3 * d + 1] - fx) <= 2.0 ** -24 * np.abs(fx) + 1e-15)
+
+
+def test_user_full_size_fp64():
+    """The user-integrand benchmark as timed: the d = 8 Gaussian written as
+    user source, a = 0.1, mu = 0.5, 50 bins, seed 0, 1e7 events, the
+    automatic launch for the compiled module, one adaptation step from the
+    uniform grid against the oracle's Gaussian (1e-12) and its refinement."""
+    d, N, M = 8, 50, 10_000_000
+    params = [0.1] + [0.5] * d
+    u = Vegas(d, N, params=params, source=ui.GAUSSIAN, seed=0, alpha=1.5)
+    E = u.edges()
+    u.iterate(M, refine=True, combine=False)
+    S1, S2, H = u.last_iteration()
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, oracle.GAUSS, params, seed=0), E, 0, M)
+    assert abs(S1 - o1) <= TOL * abs(o1), (S1, o1)
+    assert abs(S2 - o2) <= TOL * abs(o2), (S2, o2)
+    assert _hist_close(H, Ho, TOL)
+    assert np.max(np.abs(u.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
