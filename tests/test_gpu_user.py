@@ -344,19 +344,21 @@ def test_user_fp32_oscillatory_lockstep(d, N, M):
         v.refine()
 
 
-def test_user_fp32_dump_events():
+@pytest.mark.parametrize("first", [500, 10_000_000 - 5013])
+def test_user_fp32_dump_events(first):
     """Per-event records of an FP32-mixed user context: bins exact; delta is
     RN32 of the exact delta (even N); x within 2^-24 (3 w + 2 x) of the
     oracle's; w within 2^-24 (2d + 4); f is the source's FP64 value at the
-    kernel's x, rounded once to FP32."""
+    kernel's x, rounded once to FP32.  Near the start of an iteration and at
+    the end of a 1e7-event one (event counters that fill the low word)."""
     d, N = 6, 40
     params = [0.3] + list(np.linspace(1.0, 3.0, d))
     v = Vegas(d, N, params=params, source=ui.OSCILLATORY, precision="fp32_mixed", seed=3)
     pr = oracle.Problem(d, N, oracle.GAUSS, [0.1] + [0.5] * d, seed=3)
     E = oracle.run(pr, oracle.uniform_edges(d, N), 2, 20000, [1, 1], [1, 1])["edges"]
     v.set_edges(E)
-    got = v.dump_events(500, 5000 + 13, iteration=4).cpu().numpy()
-    ref = oracle.events(pr, E, 4, 500, 5000 + 13)
+    got = v.dump_events(first, 5000 + 13, iteration=4).cpu().numpy()
+    ref = oracle.events(pr, E, 4, first, 5000 + 13)
     assert np.array_equal(got[:, :d], ref[:, :d])
     assert np.array_equal(got[:, d:2 * d], ref[:, d:2 * d].astype(np.float32).astype(np.float64))
     bi = ref[:, :d].astype(np.int64)
