@@ -503,6 +503,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--mixed-only", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="only time the FP64 adaptation step (for profiling the FP64 event kernel)")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--phase-split", action="store_true",
                     help="only time iterations with/without refinement and without histograms")
@@ -523,6 +525,11 @@ def main():
         copy_probe()
     if args.phase_split:
         print(json.dumps({"phase_split": phase_split(args.steps)}), flush=True)
+        return
+    if args.fp64_only:
+        r = time_path("fp64", args.steps, args.warmup)
+        print(json.dumps({"fp64_only": {k: r[k] for k in ("ms_per_step", "events_per_s", "event_kernel_ms")}}),
+              flush=True)
         return
 
     mixed = time_path("fp32_mixed", args.steps, args.warmup)
