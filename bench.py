@@ -500,7 +500,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=800)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--fp64-only", action="store_true",
