@@ -122,10 +122,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
         row[0] = S1;
         row[1] = S2;
     }
-    // the block's histogram (replicas summed) goes into slot blockIdx mod
-    // kHistSlots with device-scope FP64 atomics: no histogram row to write and
-    // read back, and 8 slots keep the atomics on one address few
-    double* slot = a.hslots + size_t(blockIdx.x % kHistSlots) * dN;
+    // the block's histogram (replicas summed) goes into slot
+    // (blockIdx / 8) mod kHistSlots with device-scope FP64 atomics: no
+    // histogram row to write and read back, and 8 slots keep the atomics on
+    // one address few.  Workgroups go to the 8 XCDs round-robin, so each XCD's
+    // blocks spread over all the slots (blockIdx mod 8 gave each XCD one slot
+    // and ran about 1 % slower)
+    double* slot = a.hslots + size_t((blockIdx.x >> 3) % kHistSlots) * dN;
     if constexpr (FIX) {
         // bin (i, b) of the fixed layout, 16 replicas read 2 at a time
         for (int k = threadIdx.x; k < DMAX * kFixBins; k += blockDim.x) {

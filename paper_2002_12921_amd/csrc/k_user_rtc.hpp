@@ -18,7 +18,7 @@
 // context's precision: the same Philox words, exact bins, map and Jacobian
 // N^d prod W_b, the same grouped-Kahan FP64 sums of v = f w and v^2, and the
 // same per-dimension, per-bin FP64 histograms of v^2 (LDS replicas, then the
-// block's histogram added into slot blockIdx mod kHistSlots), so the
+// block's histogram added into slot (blockIdx / 8) mod kHistSlots), so the
 // reduction, refinement and combination kernels of the library serve it
 // unchanged.
 #pragma once
@@ -211,7 +211,7 @@ __device__ __forceinline__ void sample(const SampleArgs& a, const double* __rest
         row[1] = S2;
     }
     if constexpr (HIST) {
-        double* slot = a.hslots + size_t(blockIdx.x % kHistSlots) * dN;
+        double* slot = a.hslots + size_t((blockIdx.x >> 3) % kHistSlots) * dN;
         for (int k = threadIdx.x; k < dN; k += blockDim.x) {
             const int base = k << rl2;
             double h = 0.0;
