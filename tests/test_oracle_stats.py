@@ -115,3 +115,87 @@ def test_adaptive_run_hits_closed_form(orc):
     # the adapted grid concentrates bins around the peak at 0.5
     w = np.diff(E, axis=1)
     assert np.all(w[:, 25] < 0.5 / 50) and np.all(w[:, 0] > 2.0 / 50)
+
+
+# ---------------------------------------------------------------------------
+# Parameter layouts at d > 1 (sec. 3.1: Eq. lepage and its two-centre form,
+# Eq. genzdisc, Eq. productpeak), with a different value in every dimension so
+# that a parameter read from the wrong slot changes the result.
+
+MU_A3 = [0.2, 0.35, 0.6]
+MU_B3 = [0.7, 0.55, 0.25]
+GENZ3 = {"disc": ([0.7, 1.9, 1.2], [0.12, 0.31, 0.05]),
+         "peak": ([4.0, 2.5, 6.0], [0.45, 0.62, 0.3])}
+
+
+def _nested_quad(f, pts0, pts1):
+    """Integral over [0,1]^2 of f(x0, x1), as two nested adaptive quadratures
+    with the integrand's break points."""
+    inner = lambda x0: integrate.quad(lambda x1: f(x0, x1), 0, 1, points=pts1, epsabs=1e-14,
+                                      epsrel=1e-12, limit=200)[0]
+    return integrate.quad(inner, 0, 1, points=pts0, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+
+
+def test_bimodal_is_mean_of_two_gaussians_d3(orc):
+    """The two-centre integrand equals the mean of the one-centre Gaussians
+    (each pinned by separability and quadrature) at its two centres."""
+    d, a = 3, 0.13
+    pr = orc.Problem(d, 50, orc.BIMODAL, [a, *MU_A3, *MU_B3])
+    ga = orc.Problem(d, 50, orc.GAUSS, [a, *MU_A3])
+    gb = orc.Problem(d, 50, orc.GAUSS, [a, *MU_B3])
+    rng = np.random.default_rng(5)
+    pts = np.concatenate([rng.uniform(0, 1, (30, d)),
+                          np.array(MU_A3) + rng.normal(0, 0.05, (15, d)),
+                          np.array(MU_B3) + rng.normal(0, 0.05, (15, d))]).clip(0, 1)
+    for x in pts:
+        want = 0.5 * (orc.integrand(ga, x) + orc.integrand(gb, x))
+        got = orc.integrand(pr, x)
+        assert abs(got - want) <= 1e-14 * want, (x, got, want)
+
+
+def test_bimodal_integral_d2(orc):
+    """d = 2, distinct centres per dimension: quadrature of the oracle's f equals
+    1/2 [c(muA_0) c(muA_1) + c(muB_0) c(muB_1)] (each Gaussian term integrates to
+    a product of erf factors)."""
+    a, mA, mB = 0.11, [0.3, 0.62], [0.71, 0.18]
+    pr = orc.Problem(2, 50, orc.BIMODAL, [a, *mA, *mB])
+    q = _nested_quad(lambda x0, x1: orc.integrand(pr, [x0, x1]), [mA[0], mB[0]], [mA[1], mB[1]])
+    want = 0.5 * (_c(mA[0], a) * _c(mA[1], a) + _c(mB[0], a) * _c(mB[1], a))
+    assert abs(q - want) < 1e-10, (q, want)
+
+
+@pytest.mark.parametrize("kind", ["disc", "peak"])
+def test_genz_separable_d3(orc, kind):
+    """The d = 3 Genz integrand (normalisation included) is the product of the
+    one-dimensional ones with each dimension's own c_i, a_i."""
+    kid = orc.GENZ_DISC if kind == "disc" else orc.GENZ_PEAK
+    c, th = GENZ3[kind]
+    d = 3
+    pr = orc.Problem(d, 50, kid, [*c, *th])
+    ones = [orc.Problem(1, 50, kid, [c[i], th[i]]) for i in range(d)]
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        x = rng.uniform(0, 1, d)
+        if kind == "disc":   # mostly inside, where f > 0
+            x = np.array(th) + (1 - np.array(th)) * rng.uniform(0, 1, d) if rng.uniform() < 0.8 else x
+        want = np.prod([orc.integrand(ones[i], [x[i]]) for i in range(d)])
+        got = orc.integrand(pr, x)
+        assert abs(got - want) <= 1e-14 * max(want, 1e-300), (x, got, want)
+    if kind == "disc":
+        # zero exactly when some x_i <= a_i, for each dimension separately
+        for i in range(d):
+            x = np.array(th) + 0.5 * (1 - np.array(th))
+            x[i] = th[i]
+            assert orc.integrand(pr, x) == 0.0
+            x[i] = th[i] + 1e-9
+            assert orc.integrand(pr, x) > 0.0
+
+
+@pytest.mark.parametrize("kind", ["disc", "peak"])
+def test_genz_integral_d2(orc, kind):
+    """d = 2 with distinct c_i, a_i: the normalisation makes the integral one."""
+    kid = orc.GENZ_DISC if kind == "disc" else orc.GENZ_PEAK
+    c, th = ([1.4, 0.6], [0.22, 0.08]) if kind == "disc" else ([3.5, 5.0], [0.35, 0.7])
+    pr = orc.Problem(2, 50, kid, [*c, *th])
+    q = _nested_quad(lambda x0, x1: orc.integrand(pr, [x0, x1]), [th[0]], [th[1]])
+    assert abs(q - 1.0) < 1e-10, q
