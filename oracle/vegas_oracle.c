@@ -7,6 +7,7 @@
  */
 #include "vegas_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -325,10 +326,6 @@ void vo_refine(const double* H, const double* edges_in, int d, int n_bins,
 
         double total = 0.0;
         for (int b = 0; b < N; ++b) total = total + h[b];
-        if (total == 0.0) {
-            for (int k = 0; k <= N; ++k) Eo[k] = E[k];
-            continue;
-        }
 
         s[0] = (h[0] + h[1]) / 2.0;
         for (int b = 1; b < N - 1; ++b) s[b] = (h[b - 1] + h[b] + h[b + 1]) / 3.0;
@@ -336,6 +333,13 @@ void vo_refine(const double* H, const double* edges_in, int d, int n_bins,
 
         double ssum = 0.0;
         for (int b = 0; b < N; ++b) ssum = ssum + s[b];
+
+        /* nothing to adapt to: an empty histogram, or one whose total is not
+         * a finite number (the dimension keeps its grid) */
+        if (!(total > 0.0 && total <= DBL_MAX && ssum > 0.0 && ssum <= DBL_MAX)) {
+            for (int k = 0; k <= N; ++k) Eo[k] = E[k];
+            continue;
+        }
 
         double rsum = 0.0;
         for (int b = 0; b < N; ++b) {

@@ -317,6 +317,8 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
                 }
             }
         }
+        if (best < 0.0)
+            return bail(fail(VEGAS_EUNSUPPORTED, "no launch shape of the batch event kernel fits the d <= %d problems", dm));
         b->blocks = std::max(b->blocks, bk.blocks);
         b->buckets.push_back(bk);
     }

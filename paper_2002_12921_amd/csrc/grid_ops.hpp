@@ -121,7 +121,9 @@ __device__ static void refine_dim(const MergeArgs& a, int i, const double* h, co
         }
     }
     __syncthreads();
-    if (tot[0] == 0.0) return;  // empty histogram: the grid and its tables stay
+    // an empty histogram, or one whose totals are not finite (an overflowing
+    // or NaN integrand): the grid and its tables stay
+    if (!(tot[0] > 0.0 && tot[0] <= __DBL_MAX__ && tot[1] > 0.0 && tot[1] <= __DBL_MAX__)) return;
     if (t < N) Cs[t] = damp(Cs[t] / tot[1], a.alpha);
     __syncthreads();
     if (t < 64) {
@@ -200,7 +202,8 @@ __device__ static void refine_dim_wave(const MergeArgs& a, int i, double hb, dou
             sm = (hl + hb + hr) / 3.0;
     }
     const double th = wave_sum(hb), ts = wave_sum(sm);
-    if (th == 0.0) return;  // empty histogram: the grid and its tables stay
+    // empty, or not finite (an overflowing or NaN integrand): the grid and its tables stay
+    if (!(th > 0.0 && th <= __DBL_MAX__ && ts > 0.0 && ts <= __DBL_MAX__)) return;
     const double r = in ? damp(sm / ts, a.alpha) : 0.0;
     const double C = wave_inclusive_max(wave_inclusive_scan(r));  // non-decreasing under rounding
     const double R = __shfl(C, N - 1, 64);

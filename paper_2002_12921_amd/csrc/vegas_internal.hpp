@@ -24,7 +24,7 @@ constexpr int kMaxParams = 1 + 2 * kMaxDim;
 constexpr int kMaxRecords = 1024;   // recorded iterations per context
 constexpr int kBlock = 1024;        // threads per block of the event kernels
 constexpr int kMaxBlocks = 2048;    // rows of the per-block partial table
-// The event kernel adds each block's histogram into slot (block mod
+// The event kernel adds each block's histogram into slot ((block / 8) mod
 // kHistSlots) with device-scope atomics; the reduction adds the slots.
 constexpr int kHistSlots = 8;
 constexpr int kMergeThreads = 1024; // threads per block of the reduction kernel
@@ -171,7 +171,7 @@ struct SampleArgs {
     const DevConst* cst;
     const void* tab;     // double2* (FP64) or float2* (FP32), [d][N]
     double* partials;    // [gridDim.x][pstride]: S1, S2 (the histogram goes to hslots)
-    double* hslots;      // [kHistSlots][d*N]: block b adds its histogram into slot b mod kHistSlots
+    double* hslots;      // [kHistSlots][d*N]: block b adds its histogram into slot (b / 8) mod kHistSlots
     uint64_t e0;         // first event index of this launch
     uint64_t n;          // events in this launch
     uint32_t t;          // iteration index

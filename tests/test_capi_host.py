@@ -76,6 +76,27 @@ def test_lds_limit_is_unsupported():
     assert st == _lib.VEGAS_EUNSUPPORTED
 
 
+def _event_lds(prec, kind, d, N):
+    """Bytes of LDS the event kernel asks for with one histogram copy: the
+    grid table (16 bytes per bin in FP64 and for the bimodal FP32 table, else
+    8), aligned to 128, the FP64 histogram, and 16 doubles of wave partials."""
+    tab = d * N * (16 if (prec == "fp64" or kind == "bimodal") else 8)
+    return ((tab + 127) // 128) * 128 + d * N * 8 + 16 * 8
+
+
+@pytest.mark.parametrize("prec,kind,d,N", [("fp64", "gauss", 31, 220), ("fp64", "gauss", 44, 155),
+                                           ("fp64", "gauss", 62, 110), ("fp32_mixed", "gauss", 53, 193),
+                                           ("fp32_mixed", "gauss", 53, 192), ("fp64", "gauss", 64, 104)])
+def test_lds_limit_matches_the_launch(prec, kind, d, N):
+    """Sizes are admitted exactly when the event kernel's smallest launch fits
+    the 160 KiB of LDS of a compute unit (near-limit cases on both sides)."""
+    params = [0.1] + [0.5] * d
+    desc, keep = make_desc(d, N, kind, params, prec)
+    st, _ = _size(desc)
+    fits = _event_lds(prec, kind, d, N) <= 160 * 1024
+    assert st == (_lib.VEGAS_OK if fits else _lib.VEGAS_EUNSUPPORTED), (_event_lds(prec, kind, d, N), st)
+
+
 def test_genz_parameter_checks():
     d, keep = make_desc(2, 50, "genz_disc", [1.0, 1.0, 0.5, 1.0], "fp64")   # a = 1 not < 1
     assert _size(d)[0] == _lib.VEGAS_EINVAL

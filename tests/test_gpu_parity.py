@@ -429,12 +429,21 @@ def test_nonfinite_is_reported():
     # integrand whose FP64 normalisation overflows: a tiny width in many dims.
     d = 40
     v = Vegas(d, 4, "gauss", [1e-9] + [0.5] * d, "fp64")
-    v.iterate(1000)
+    E0 = v.edges()
+    v.iterate(1000, refine=True)
     r = v.result(allow_nonfinite=True)
     assert r["n_nonfinite"] == 1 and r["n_combined"] == 0
     from paper_2002_12921_amd._lib import VegasError
     with pytest.raises(VegasError, match="ENONFINITE"):
         v.result()
+    # the histograms are not finite: the refinement keeps the grid (and its
+    # tables: the next iteration is as on the uniform grid)
+    assert np.array_equal(v.edges(), E0)
+    _, _, H = v.last_iteration()
+    assert not np.all(np.isfinite(H))
+    # the state stays loadable (its edges are valid)
+    w = Vegas(d, 4, "gauss", [1e-9] + [0.5] * d, "fp64")
+    w.set_state(v.get_state())
 
 
 @pytest.mark.parametrize("d", [8, 5, 12])

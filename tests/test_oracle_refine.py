@@ -114,3 +114,23 @@ def test_alpha0_equal_count_closed_form(orc):
             b -= 1
         want = E[0, b] + (u - b) * (E[0, b + 1] - E[0, b])
         assert abs(En[k] - want) < 1e-14, (k, En[k], want)
+
+
+def test_nonfinite_histogram_keeps_the_grid(orc):
+    """A dimension whose histogram holds an infinity or a NaN (an integrand that
+    overflowed) has nothing finite to adapt to and keeps its edges, as an empty
+    one does; the other dimensions refine as usual."""
+    rng = np.random.default_rng(3)
+    d, N = 4, 20
+    E = _random_grid(rng, d, N)
+    H = rng.exponential(1.0, (d, N))
+    H[0, 3] = np.inf
+    H[1, 7] = np.nan
+    H[2, :] = 0.0
+    En = orc.refine(H, E, 1.5)
+    assert np.array_equal(En[:3], E[:3])
+    ref3 = orc.refine(H[3:], E[3:], 1.5)
+    assert np.array_equal(En[3], ref3[0]) and not np.array_equal(En[3], E[3])
+    # a finite total that is too large to smooth (the smoothed sum overflows)
+    H2 = np.full((1, N), 1.7e308)
+    assert np.array_equal(orc.refine(H2, E[:1], 1.5), E[:1])
