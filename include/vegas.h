@@ -81,6 +81,8 @@ enum { VEGAS_FP64 = 0, VEGAS_FP32_MIXED = 1 };
 #define VEGAS_NO_COMBINE 4u  /* (with CHUNK_END) record it but keep it out of the combination */
 #define VEGAS_REFINE 8u      /* (with CHUNK_END) refine the grid from this iteration's histograms */
 #define VEGAS_NO_HIST 16u    /* no histograms this iteration (every chunk of it); not with REFINE */
+#define VEGAS_NO_RECORD 32u  /* (with CHUNK_END) keep the estimate as the last iteration's only: no record
+                                slot is used and the combination does not see it */
 
 typedef struct {
     int32_t dim;          /* d */
@@ -157,7 +159,10 @@ vegas_status vegas_init_user(vegas_ctx** out, const vegas_desc* desc, const char
  * are copied there, NUL-terminated and cut to log_bytes. */
 vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precision, char* log, size_t log_bytes);
 
-/* Run n_events events (1 <= n_events <= 2^40) of the current iteration t.
+/* The per-event stage of one integration pass (sec. 2.2: random points,
+ * weighted by the grid's Jacobian, feed the integral's sums and the
+ * accumulators the refinement later reads), as one call or in chunks.
+ * Run n_events events (1 <= n_events <= 2^40) of the current iteration t.
  * Event e draws, for each group j of four dimensions,
  * Philox4x32-10(counter = (e mod 2^32, e div 2^32, t, p*256 + j),
  * key = (seed mod 2^32, seed div 2^32)); dimension i takes word i mod 4 of
@@ -168,10 +173,12 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precisi
  * VEGAS_NO_HIST skips the per-bin histograms (for an iteration on a frozen
  * grid: the estimate is unchanged); it must be given on every chunk of the
  * iteration or on none, never with REFINE, and the iteration's histogram row
- * (vegas_last_iteration_device) then reads zero and vegas_refine has nothing
- * to refine from.  EINVAL otherwise. 
+ * (vegas_get_iteration) then reads zero and vegas_refine has nothing
+ * to refine from.  EINVAL otherwise.
  * At CHUNK_END: I_t = S1/M, var_t = (S2/M - I_t^2)/(M-1) over the M events
- * of the iteration (M >= 2), the iteration is recorded and t advances.
+ * of the iteration (M >= 2), the iteration is recorded and t advances.  A
+ * context records at most 1024 iterations (then ESTATE until
+ * vegas_reset_results); VEGAS_NO_RECORD iterations do not count.
  * The call only enqueues kernel launches (no copies, no memsets, no host
  * waits unless timing is enabled), so it can be recorded by stream capture
  * into a HIP graph.  Its host-side bookkeeping (t, the record index) advances
@@ -180,11 +187,15 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precisi
 vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,
                            vegas_stream_t stream);
 
-/* Refine the grid from the histograms of the last completed iteration
+/* The refinement stage that follows a finished pass (sec. 2.2: once the
+ * integration pass is done, the way points are generated is adapted): the
+ * grid is refined from the histograms of the last completed iteration
  * (ESTATE if there is none, or if they were already used for a refinement). */
 vegas_status vegas_refine(vegas_ctx* ctx, vegas_stream_t stream);
 
-/* Copy the combined result to *host_out.  Synchronises.  Returns
+/* The result as the paper reports it, value +- error (Table 1): the
+ * inverse-variance combination of the combined iterations.
+ * Copy the combined result to *host_out.  Synchronises.  Returns
  * VEGAS_ENONFINITE (with *host_out filled) if any recorded iteration was not
  * finite. */
 vegas_status vegas_result(vegas_ctx* ctx, vegas_result_t* host_out, vegas_stream_t stream);
@@ -193,19 +204,39 @@ vegas_status vegas_result(vegas_ctx* ctx, vegas_result_t* host_out, vegas_stream
 vegas_status vegas_reset_results(vegas_ctx* ctx, vegas_stream_t stream);
 
 /* Replace the integrand parameters from device memory (n_params values, FP64
- * if is_fp32 == 0, else FP32; same layout as vegas_desc.params). */
+ * if is_fp32 == 0, else FP32; same layout as vegas_desc.params).  One kernel
+ * launch stores them, their derived constants and the grid tables. */
 vegas_status vegas_set_params_device(vegas_ctx* ctx, const void* dev_params, int32_t n_params,
                                      int32_t is_fp32, vegas_stream_t stream);
 
-/* Write (I_t, sigma_t) of the last recorded iteration to dev_out[2] (device). */
+/* Copy the context's current integrand parameters (FP64, n_params values) to
+ * device memory dev_out. */
+vegas_status vegas_get_params_device(vegas_ctx* ctx, double* dev_out, vegas_stream_t stream);
+
+/* Change counters of the context: *grid_version advances whenever the edges
+ * change (a refinement, vegas_set_edges, vegas_set_state), *params_version
+ * whenever the integrand parameters do (vegas_set_params_device).  A caller
+ * that keeps work for later (an adjoint after a forward pass) compares them
+ * to know whether the context still holds what it used.  Either pointer may
+ * be NULL. */
+vegas_status vegas_get_versions(const vegas_ctx* ctx, int64_t* grid_version, int64_t* params_version);
+
+/* Write (I_t, sigma_t) of the last finished iteration (recorded or
+ * VEGAS_NO_RECORD) to dev_out[2] (device). */
 vegas_status vegas_last_iteration_device(vegas_ctx* ctx, double* dev_out, vegas_stream_t stream);
 
 /* Adjoint of the estimate of iteration `iteration` over events [0, n_events)
- * at fixed samples and the current (frozen) grid, Gaussian integrand only:
+ * at fixed samples and the current (frozen) grid and parameters, Gaussian
+ * integrand only (the derivative of Eq. lepage's estimate with respect to its
+ * centre and width):
  * dev_grad[j] = gout * (1/M) sum_e w_e df/dtheta_j(x_e), theta = (mu[0..d-1], a),
- * with gout = *dev_gout (device FP64 scalar).  dev_grad is device FP64[d+1]. */
+ * with gout = *dev_gout (device FP64 scalar).  dev_grad is device memory of
+ * d+1 values, FP64 (grad_fp32 == 0) or FP32 (each rounded once from the FP64
+ * sum, for FP32 parameters).  The per-event terms are summed in FP64 in both
+ * precisions of the context. */
 vegas_status vegas_adjoint(vegas_ctx* ctx, int64_t iteration, int64_t n_events,
-                           const double* dev_gout, double* dev_grad, vegas_stream_t stream);
+                           const double* dev_gout, void* dev_grad, int32_t grad_fp32,
+                           vegas_stream_t stream);
 
 /* Per-event record of events [first, first+count) of iteration `iteration`
  * on the current grid, into device FP64 dev_out[count][3d+2]:

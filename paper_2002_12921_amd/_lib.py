@@ -19,12 +19,13 @@ STATUS_NAMES = {0: "VEGAS_OK", -1: "VEGAS_EINVAL", -2: "VEGAS_ESTATE", -3: "VEGA
 
 GAUSS, BIMODAL, GENZ_DISC, GENZ_PEAK, USER = 0, 1, 2, 3, 4
 FP64, FP32_MIXED = 0, 1
-CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST = 1, 2, 3, 4, 8, 16
+CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST, NO_RECORD = 1, 2, 3, 4, 8, 16, 32
 
 # every symbol include/vegas.h declares
 EXPORTS = [
     "vegas_workspace_size", "vegas_init_grid", "vegas_init_user", "vegas_user_compile", "vegas_iterate", "vegas_refine", "vegas_result",
-    "vegas_reset_results", "vegas_set_params_device", "vegas_last_iteration_device",
+    "vegas_reset_results", "vegas_set_params_device", "vegas_get_params_device", "vegas_get_versions",
+    "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
     "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
     "vegas_get_iteration_index", "vegas_set_launch", "vegas_set_hist_replicas", "vegas_get_launch",
@@ -86,7 +87,9 @@ def lib() -> ctypes.CDLL:
         "vegas_reset_results": [vp, vp],
         "vegas_set_params_device": [vp, vp, i32, i32, vp],
         "vegas_last_iteration_device": [vp, vp, vp],
-        "vegas_adjoint": [vp, i64, i64, vp, vp, vp],
+        "vegas_get_params_device": [vp, vp, vp],
+        "vegas_get_versions": [vp, P(i64), P(i64)],
+        "vegas_adjoint": [vp, i64, i64, vp, vp, i32, vp],
         "vegas_dump_events": [vp, i64, i64, i64, vp, vp],
         "vegas_get_edges": [vp, pd, vp],
         "vegas_set_edges": [vp, pd, vp],

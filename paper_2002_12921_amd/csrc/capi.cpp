@@ -116,6 +116,9 @@ struct vegas_ctx {
     bool chunk_no_hist = false;  // the open iteration runs without histograms
     int64_t chunk_events = 0; // events already run in the open iteration
     bool has_hist = false;    // histograms of a finished iteration not yet refined from
+    bool has_last = false;    // an iteration has finished (recorded or not)
+    int64_t grid_version = 0;   // advances whenever the edges change
+    int64_t params_version = 0; // advances whenever the integrand parameters change
     int blocks_user = 0;
     int blocks_auto = 0;
     int threads = kBlock;     // threads per block of the event kernel
@@ -199,7 +202,6 @@ SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
     a.key1 = uint32_t(c->seed >> 32);
     a.d = c->d;
     a.N = c->N;
-    a.pstride = c->L.pstride;
     a.hrep_log2 = c->hrep_user >= 0 ? c->hrep_user : c->hrep_log2;
     a.hist = no_hist ? 0 : 1;
     return a;
@@ -222,6 +224,7 @@ MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
     a.alpha = c->alpha;
     a.M = M;
     a.rows = rows;
+    a.rstride = 2;  // the rows hold S1, S2; the histogram is in hslots
     a.d = c->d;
     a.N = c->N;
     a.pstride = c->L.pstride;
@@ -432,12 +435,14 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
 {
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40] (got %lld)", (long long)n);
-    if (flags & ~uint32_t(VEGAS_CHUNK_BEGIN | VEGAS_CHUNK_END | VEGAS_NO_COMBINE | VEGAS_REFINE | VEGAS_NO_HIST))
+    if (flags & ~uint32_t(VEGAS_CHUNK_BEGIN | VEGAS_CHUNK_END | VEGAS_NO_COMBINE | VEGAS_REFINE | VEGAS_NO_HIST |
+                          VEGAS_NO_RECORD))
         return fail(VEGAS_EINVAL, "unknown flags 0x%x", flags);
     const bool begin = flags & VEGAS_CHUNK_BEGIN, end = flags & VEGAS_CHUNK_END;
     const bool no_hist = flags & VEGAS_NO_HIST;
-    if ((flags & (VEGAS_NO_COMBINE | VEGAS_REFINE)) && !end)
-        return fail(VEGAS_EINVAL, "REFINE / NO_COMBINE only apply with CHUNK_END");
+    const bool no_record = flags & VEGAS_NO_RECORD;
+    if ((flags & (VEGAS_NO_COMBINE | VEGAS_REFINE | VEGAS_NO_RECORD)) && !end)
+        return fail(VEGAS_EINVAL, "REFINE / NO_COMBINE / NO_RECORD only apply with CHUNK_END");
     if (no_hist && (flags & VEGAS_REFINE)) return fail(VEGAS_EINVAL, "REFINE needs the histograms (NO_HIST given)");
     if (begin && c->in_chunk) return fail(VEGAS_ESTATE, "CHUNK_BEGIN while an iteration is open");
     if (!begin && !c->in_chunk) return fail(VEGAS_ESTATE, "no open iteration: start with CHUNK_BEGIN");
@@ -447,7 +452,7 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     const int64_t M = e0 + n;
     if (M > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "iteration exceeds 2^40 events");
     if (end && M < 2) return fail(VEGAS_EINVAL, "an iteration needs at least 2 events");
-    if (end && c->rec_idx >= kMaxRecords)
+    if (end && !no_record && c->rec_idx >= kMaxRecords)
         return fail(VEGAS_ESTATE, "%d iterations recorded: call vegas_reset_results", kMaxRecords);
     if (c->t >= (int64_t(1) << 32)) return fail(VEGAS_ESTATE, "iteration index exhausted");
 
@@ -459,7 +464,8 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     VEGAS_HIP(launch_event_kernel(c, a, blocks, s));
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
     int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
-             ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0) | (no_hist ? MERGE_NO_HIST : 0);
+             ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0) | (no_hist ? MERGE_NO_HIST : 0) |
+             (no_record ? MERGE_NO_RECORD : 0);
     VEGAS_HIP(launch_merge(merge_args(c, blocks, mf, double(M)), s));
     if (timed) {
         VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 2], s));
@@ -471,8 +477,10 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
     c->chunk_no_hist = no_hist;
     if (end) {
         c->t += 1;
-        c->rec_idx += 1;
+        if (!no_record) c->rec_idx += 1;
         c->has_hist = !(flags & VEGAS_REFINE) && !no_hist;
+        c->has_last = true;
+        if (flags & VEGAS_REFINE) c->grid_version += 1;
         c->chunk_events = 0;
     }
     return VEGAS_OK;
@@ -513,6 +521,7 @@ vegas_status vegas_refine(vegas_ctx* c, vegas_stream_t stream)
     if (!c->has_hist) return fail(VEGAS_ESTATE, "no completed iteration whose histograms are unused");
     VEGAS_HIP(launch_refine(merge_args(c, 1, 0, 0.0), static_cast<hipStream_t>(stream)));
     c->has_hist = false;
+    c->grid_version += 1;
     return VEGAS_OK;
 }
 
@@ -553,23 +562,42 @@ vegas_status vegas_set_params_device(vegas_ctx* c, const void* dev_params, int32
     const int want = c->kind == USER ? c->n_params : expected_params(c->kind, c->d);
     if (n != want) return fail(VEGAS_EINVAL, "expected %d params, got %d", want, n);
     if (n == 0) return VEGAS_OK;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    VEGAS_HIP(launch_params_from(dev_params, n, is_fp32 ? 1 : 0, c->P.params, s));
-    VEGAS_HIP(launch_prepare(c->prec, c->kind, c->d, c->N, c->P.params, c->P.cst, s));
-    VEGAS_HIP(launch_build_tables(c->P, c->kind, c->d, c->N, s));  // FP32 tables hold centre offsets
+    // parameters, derived constants and the tables (FP32 entries are offsets
+    // from the centres) in one launch
+    VEGAS_HIP(launch_set_params(c->prec, c->kind, c->d, c->N, dev_params, n, is_fp32 ? 1 : 0, c->P,
+                                static_cast<hipStream_t>(stream)));
+    c->params_version += 1;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_params_device(vegas_ctx* c, double* dev_out, vegas_stream_t stream)
+{
+    if (!c || !dev_out) return fail(VEGAS_EINVAL, "NULL argument");
+    const int n = c->kind == USER ? c->n_params : expected_params(c->kind, c->d);
+    if (n == 0) return VEGAS_OK;
+    VEGAS_HIP(hipMemcpyAsync(dev_out, c->P.params, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                             static_cast<hipStream_t>(stream)));
+    return VEGAS_OK;
+}
+
+vegas_status vegas_get_versions(const vegas_ctx* c, int64_t* grid_version, int64_t* params_version)
+{
+    if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
+    if (grid_version) *grid_version = c->grid_version;
+    if (params_version) *params_version = c->params_version;
     return VEGAS_OK;
 }
 
 vegas_status vegas_last_iteration_device(vegas_ctx* c, double* dev_out, vegas_stream_t stream)
 {
     if (!c || !dev_out) return fail(VEGAS_EINVAL, "NULL argument");
-    if (c->rec_idx == 0) return fail(VEGAS_ESTATE, "no recorded iteration");
+    if (!c->has_last && c->rec_idx == 0) return fail(VEGAS_ESTATE, "no finished iteration");
     VEGAS_HIP(launch_copy_last(c->P.result, dev_out, static_cast<hipStream_t>(stream)));
     return VEGAS_OK;
 }
 
-vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const double* dev_gout, double* dev_grad,
-                           vegas_stream_t stream)
+vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const double* dev_gout, void* dev_grad,
+                           int32_t grad_fp32, vegas_stream_t stream)
 {
     if (!c || !dev_gout || !dev_grad) return fail(VEGAS_EINVAL, "NULL argument");
     if (c->kind != VEGAS_GAUSS) return fail(VEGAS_EUNSUPPORTED, "the adjoint is implemented for the Gaussian integrand");
@@ -589,6 +617,7 @@ vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const dou
     a.key1 = uint32_t(c->seed >> 32);
     a.d = c->d;
     a.N = c->N;
+    a.grad_fp32 = grad_fp32 ? 1 : 0;
     VEGAS_HIP(launch_adjoint(c->prec, a, sample_blocks(c, n), static_cast<hipStream_t>(stream)));
     return VEGAS_OK;
 }
@@ -642,6 +671,7 @@ vegas_status vegas_set_edges(vegas_ctx* c, const double* host, vegas_stream_t st
     hipStream_t s = static_cast<hipStream_t>(stream);
     VEGAS_HIP(hipMemcpyAsync(c->P.edges, host, sizeof(double) * c->d * (c->N + 1), hipMemcpyHostToDevice, s));
     VEGAS_HIP(launch_build_tables(c->P, c->kind, c->d, c->N, s));
+    c->grid_version += 1;
     return VEGAS_OK;
 }
 
@@ -724,6 +754,8 @@ vegas_status vegas_set_state(vegas_ctx* c, const void* host_buf, size_t bytes, v
     c->t = h.t;
     c->rec_idx = h.rec_idx;
     c->has_hist = h.has_hist != 0;
+    c->has_last = h.rec_idx > 0;
+    c->grid_version += 1;
     return VEGAS_OK;
 }
 

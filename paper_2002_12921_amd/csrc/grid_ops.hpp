@@ -8,18 +8,24 @@ namespace vegas {
 
 // Statistics of one iteration (Lepage 1978 sec. 3): I_t = S1/M and the
 // variance of that mean, var_t = (S2/M - I_t^2)/(M - 1).  The iteration is
-// recorded; the combination over recorded iterations runs in k_combine.
+// recorded (unless NO_RECORD: then it only becomes the last iteration's
+// estimate); the combination over recorded iterations runs in k_combine.
 __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2)
 {
     const double M = a.M;
     const double I = S1 / M;
     const double var = (S2 / M - I * I) / (M - 1.0);
     const bool ok = isfinite(I) && isfinite(var);
+    DevResult* R = a.result;
+    if (a.flags & MERGE_NO_RECORD) {
+        R->last_integral = I;
+        R->last_var = var;
+        return;
+    }
     const int rec = a.rec_idx;
     a.records[2 * rec] = I;
     a.records[2 * rec + 1] = var;
     a.rec_flag[rec] = (ok && !(a.flags & MERGE_NO_COMBINE)) ? 1 : 0;
-    DevResult* R = a.result;
     R->last_integral = I;
     R->last_var = var;
     R->n_iter = rec + 1;
@@ -34,11 +40,10 @@ __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2
 //         (h = 1/2 for odd N, else 0),
 //         (RN32((g - cA) S), [RN32((g - cB) S),] W 2^ws)
 //   The event kernel forms (x - c) S = RN32(lo) W 2^ws + first entry.
-__device__ __forceinline__ void write_table_entry(int i, int b, double lo, double hi, const DevConst* __restrict__ c,
-                                                  int kind, int N, double2* tab64, float* tab32)
+__device__ __forceinline__ void write_table_entry(int i, int b, double lo, double hi, double cA, double cB,
+                                                  float dscale32, int kind, int N, double2* tab64, float* tab32)
 {
-    const double cA = c->cA64[i], cB = c->cB64[i];
-    const double sw = 1.0 / double(c->dscale32);  // 2^ws
+    const double sw = 1.0 / double(dscale32);  // 2^ws
     const double S = sw * 0x1p32;
     const double h = (N & 1) ? 0x1p-33 : 0.0;     // h / 2^32
     const double w = hi - lo;
@@ -54,10 +59,31 @@ __device__ __forceinline__ void write_table_entry(int i, int b, double lo, doubl
     }
 }
 
+__device__ __forceinline__ void write_table_entry(int i, int b, double lo, double hi, const DevConst* __restrict__ c,
+                                                  int kind, int N, double2* tab64, float* tab32)
+{
+    write_table_entry(i, b, lo, hi, c->cA64[i], c->cB64[i], c->dscale32, kind, N, tab64, tab32);
+}
+
 __device__ static void write_tables(int i, const double* E, const DevConst* __restrict__ c, int kind,
                                     int N, double2* tab64, float* tab32)
 {
     for (int b = threadIdx.x; b < N; b += blockDim.x) write_table_entry(i, b, E[b], E[b + 1], c, kind, N, tab64, tab32);
+}
+
+// Scale of the FP32 table's widths: 2^-ws with ws = round(log2 N), so the
+// product of d scaled widths stays near one.
+__device__ __forceinline__ float width_scale32(int N) { return ldexpf(1.0f, -int(rint(log2(double(N))))); }
+
+// The table centres of dimension i from the raw parameters q (layouts of
+// vegas_desc.params): GAUSS mu_i; BIMODAL muA_i and muB_i; Genz a_i; USER 0.
+__device__ __forceinline__ void table_centres(int kind, int d, int i, const double* q, double& cA, double& cB)
+{
+    cA = 0.0;
+    cB = 0.0;
+    if (kind == GAUSS || kind == BIMODAL) cA = q[1 + i];
+    if (kind == BIMODAL) cB = q[1 + d + i];
+    if (kind == GENZ_DISC || kind == GENZ_PEAK) cA = q[d + i];
 }
 
 // Damping of the refinement: r(s) = ((s - 1)/ln s)^alpha, r(0) = 0, r(1) = 1.
@@ -322,7 +348,7 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
         const int col = lane & 1;
         double s = 0.0, c = 0.0;
         for (int r = int(threadIdx.x) >> 1; r < a.rows; r += kMergeThreads / 2)
-            twosum_add(s, c, a.partials[size_t(r) * a.pstride + col]);
+            twosum_add(s, c, a.partials[size_t(r) * a.rstride + col]);
 #pragma unroll
         for (int o = 2; o < 64; o <<= 1) {
             const double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
@@ -341,18 +367,18 @@ __device__ static void merge_group(const MergeArgs& a, const int g)
         for (; r + 31 * kWaves < a.rows; r += 32 * kWaves) {
             double v[32];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) v[u] = base[size_t(r + u * kWaves) * a.pstride];
+            for (int u = 0; u < 32; ++u) v[u] = base[size_t(r + u * kWaves) * a.rstride];
 #pragma unroll
             for (int u = 0; u < 32; ++u) twosum_add(s, c, v[u]);
         }
         for (; r + 7 * kWaves < a.rows; r += 8 * kWaves) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = base[size_t(r + u * kWaves) * a.pstride];
+            for (int u = 0; u < 8; ++u) v[u] = base[size_t(r + u * kWaves) * a.rstride];
 #pragma unroll
             for (int u = 0; u < 8; ++u) twosum_add(s, c, v[u]);
         }
-        for (; r < a.rows; r += kWaves) twosum_add(s, c, base[size_t(r) * a.pstride]);
+        for (; r < a.rows; r += kWaves) twosum_add(s, c, base[size_t(r) * a.rstride]);
         ws_s[wave][col] = s;
         ws_c[wave][col] = c;
     }

@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_batch_finish(BatchArgs a, int
     m.d = pr.d;
     m.N = pr.N;
     m.pstride = pr.pstride;
+    m.rstride = pr.pstride;  // batch rows carry S1, S2 and H
     m.kind = kind;
     m.flags = MERGE_BEGIN | MERGE_END | flags;
     m.rec_idx = rec_idx;

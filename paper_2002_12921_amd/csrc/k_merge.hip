@@ -28,19 +28,17 @@ __global__ __launch_bounds__(kMergeThreads) void k_refine(MergeArgs a)
     refine_any(a, i, h, Eo);
 }
 
-// Derived constants of the integrand (see DevConst).
-__global__ void k_prepare(int prec, int kind, int d, int N, const double* __restrict__ q,
-                          DevConst* __restrict__ c)
+// Derived constants of the integrand (see DevConst), by one thread.
+__device__ static void prepare_consts(int prec, int kind, int d, int N, const double* __restrict__ q,
+                                      DevConst* __restrict__ c)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double pi = 3.14159265358979323846;
     const double log2e = 1.4426950408889634074;
     c->n_bins = N;
     c->pad1 = 0;
     c->pad2 = 0.0;
-    // FP32 widths are scaled by 2^ws, ws = round(log2 N), so their product stays near one
+    c->dscale32 = width_scale32(N);
     const int ws = int(rint(log2(double(N))));
-    c->dscale32 = ldexpf(1.0f, -ws);
     double nd = 1.0;
     for (int i = 0; i < d; ++i) nd = nd * double(N);
     c->Cw = prec == FP64 ? nd : ldexp(nd, -ws * d);
@@ -51,6 +49,7 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
         c->p1_64[i] = c->p2_64[i] = c->cA64[i] = c->cB64[i] = 0.0;
         c->p1_32[i] = c->p2_32[i] = 0.0f;
     }
+    for (int i = 0; i < d; ++i) table_centres(kind, d, i, q, c->cA64[i], c->cB64[i]);
     if (kind == GAUSS || kind == BIMODAL) {
         const double a = q[0];
         Cf = pow(a * sqrt(pi), double(-d));
@@ -61,11 +60,8 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
         c->kexp32 = float(log2e / (a * a));
         c->ka32 = float(1.0 / (a * a));
         for (int i = 0; i < d; ++i) {
-            c->p1_64[i] = c->cA64[i] = q[1 + i];
-            if (kind == BIMODAL) {
-                c->cB64[i] = q[1 + d + i];
-                c->p2_64[i] = q[1 + d + i] - q[1 + i];  // FP64 map: u_B = u_A - (muB - muA)
-            }
+            c->p1_64[i] = q[1 + i];
+            if (kind == BIMODAL) c->p2_64[i] = q[1 + d + i] - q[1 + i];  // FP64 map: u_B = u_A - (muB - muA)
         }
     } else if (kind == GENZ_DISC) {
         // nu exp(sum c x) = [nu e^{sum c a}] exp(sum c (x - a)); per dimension
@@ -76,7 +72,7 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
             const double cc = q[i], aa = q[d + i];
             Cf = Cf * (cc / expm1(cc * (1.0 - aa)));
             c->p1_64[i] = cc;
-            c->p2_64[i] = c->cA64[i] = aa;
+            c->p2_64[i] = aa;
         }
     } else if (kind == USER) {
         // the caller's f carries its own normalisation; C = N^d
@@ -88,12 +84,44 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
             const double cc = q[i], aa = q[d + i];
             Cf = Cf * (cc / (atan(cc * (1.0 - aa)) + atan(cc * aa)));
             c->p1_64[i] = cc * cc;
-            c->p2_64[i] = c->cA64[i] = aa;
+            c->p2_64[i] = aa;
             c->p1_32[i] = float(cc * cc);
         }
     }
     c->Cf = Cf;
     c->C = Cf * c->Cw;
+}
+
+__global__ void k_prepare(int prec, int kind, int d, int N, const double* __restrict__ q,
+                          DevConst* __restrict__ c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) prepare_consts(prec, kind, d, N, q, c);
+}
+
+// New integrand parameters in one launch (block i: dimension i): every block
+// reads the caller's n values (FP64, or FP32 widened exactly), block 0 stores
+// them and the derived constants, and each block rebuilds its dimension's
+// tables (whose FP32 entries are offsets from the parameters' centres) with
+// the centres taken from the parameters themselves, so no block waits for
+// another.
+__global__ __launch_bounds__(256) void k_set_params(int prec, int kind, int d, int N, const void* __restrict__ src,
+                                                    int n, int is_fp32, ProblemPtrs p)
+{
+    __shared__ double q[kMaxParams];
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        q[k] = is_fp32 ? double(static_cast<const float*>(src)[k]) : static_cast<const double*>(src)[k];
+    __syncthreads();
+    const int i = blockIdx.x;
+    if (i == 0) {
+        for (int k = threadIdx.x; k < n; k += blockDim.x) p.params[k] = q[k];
+        if (threadIdx.x == 0) prepare_consts(prec, kind, d, N, q, p.cst);
+    }
+    double cA, cB;
+    table_centres(kind, d, i, q, cA, cB);
+    const float ds = width_scale32(N);
+    const double* E = p.edges + size_t(i) * (N + 1);
+    for (int b = threadIdx.x; b < N; b += blockDim.x)
+        write_table_entry(i, b, E[b], E[b + 1], cA, cB, ds, kind, N, p.tab64, p.tab32);
 }
 
 // Uniform grid E_k = k/N and a clean state (tables: k_build_tables).
@@ -133,12 +161,6 @@ __global__ void k_build_tables(ProblemPtrs p, int kind, int N)
 __global__ void k_combine(const double* records, const int32_t* rec_flag, int n_rec, DevResult* R)
 {
     if (threadIdx.x == 0) combine_records(records, rec_flag, n_rec, R);
-}
-
-__global__ void k_params_from(const void* src, int n, int is_fp32, double* dst)
-{
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        dst[k] = is_fp32 ? double(static_cast<const float*>(src)[k]) : static_cast<const double*>(src)[k];
 }
 
 __global__ void k_reset_results(double* records, int32_t* rec_flag, DevResult* R)
@@ -207,9 +229,10 @@ hipError_t launch_combine(const double* records, const int32_t* rec_flag, int n_
     return hipGetLastError();
 }
 
-hipError_t launch_params_from(const void* src, int n, int is_fp32, double* dst, hipStream_t s)
+hipError_t launch_set_params(int prec, int kind, int d, int N, const void* src, int n, int is_fp32,
+                             const ProblemPtrs& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_params_from, dim3(1), dim3(256), 0, s, src, n, is_fp32, dst);
+    hipLaunchKernelGGL(k_set_params, dim3(d), dim3(256), 0, s, prec, kind, d, N, src, n, is_fp32, p);
     return hipGetLastError();
 }
 

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
     // block_sum synchronises, which also completes every histogram atomic
     const double S1 = block_sum(s1 - c1, red);
     const double S2 = block_sum(s2 - c2, red);
-    double* row = a.partials + size_t(blockIdx.x) * a.pstride;
+    double* row = a.partials + size_t(blockIdx.x) * 2;
     if (threadIdx.x == 0) {
         row[0] = S1;
         row[1] = S2;
@@ -253,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 // Final step of the adjoint, scaled by gout/M: one wave per component j (and
 // j + 16, ...), lane l adding rows l, l + 64, ... in order with two-sums, then
 // an exact two-sum butterfly across the wave (the same pair on every lane).
+// The gradient is stored in FP64, or rounded once to FP32 (grad_fp32).
 __global__ __launch_bounds__(kMergeThreads) void k_adjoint_merge(AdjointArgs a, int rows)
 {
     const double scale = *a.gout / double(a.n);
@@ -266,7 +267,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_adjoint_merge(AdjointArgs a, 
             twosum_add(s, c, s2);
             c += c2;
         }
-        if (lane == 0) a.grad[j] = (s + c) * scale;
+        if (lane == 0) {
+            const double g = (s + c) * scale;
+            if (a.grad_fp32)
+                static_cast<float*>(a.grad)[j] = float(g);
+            else
+                static_cast<double*>(a.grad)[j] = g;
+        }
     }
 }
 

@@ -205,7 +205,7 @@ __device__ __forceinline__ void sample(const SampleArgs& a, const double* __rest
     // block_sum synchronises, which also completes every histogram atomic
     const double S1 = block_sum(s1 - c1, red);
     const double S2 = block_sum(s2 - c2, red);
-    double* row = a.partials + size_t(blockIdx.x) * a.pstride;
+    double* row = a.partials + size_t(blockIdx.x) * 2;
     if (threadIdx.x == 0) {
         row[0] = S1;
         row[1] = S2;

@@ -75,7 +75,7 @@ struct Layout {
     size_t edges;     // double[d][N+1]
     size_t tab64;     // double2[d][N]  (E_b, E_{b+1}-E_b)
     size_t tab32;     // float2 or float4 [d][N]  (offsets from the centres, scaled width)
-    size_t partials;  // double[kMaxBlocks][pstride]
+    size_t partials;  // double[kMaxBlocks][2]  per-block (S1, S2) of the event kernel
     size_t hslots;    // double[kHistSlots][d*N]  histogram accumulators of the event kernel
     size_t acc;       // double[2][pstride]   chunk accumulators (hi, lo)
     size_t last;      // double[pstride]      S1, S2, H of the last completed iteration
@@ -100,7 +100,7 @@ inline Layout make_layout(int d, int N)
     L.edges = take(sizeof(double) * d * (N + 1));
     L.tab64 = take(sizeof(double) * 2 * d * N);
     L.tab32 = take(sizeof(float) * 4 * d * N);
-    L.partials = take(sizeof(double) * size_t(kMaxBlocks) * ps);
+    L.partials = take(sizeof(double) * size_t(kMaxBlocks) * 2);
     L.hslots = take(sizeof(double) * size_t(kHistSlots) * d * N);
     L.acc = take(sizeof(double) * 2 * size_t(ps));
     L.last = take(sizeof(double) * size_t(ps));
@@ -170,14 +170,14 @@ inline ProblemPtrs problem_ptrs(void* ws, const Layout& L)
 struct SampleArgs {
     const DevConst* cst;
     const void* tab;     // double2* (FP64) or float2* (FP32), [d][N]
-    double* partials;    // [gridDim.x][pstride]: S1, S2 (the histogram goes to hslots)
+    double* partials;    // [gridDim.x][2]: S1, S2 (the histogram goes to hslots)
     double* hslots;      // [kHistSlots][d*N]: block b adds its histogram into slot (b / 8) mod kHistSlots
     uint64_t e0;         // first event index of this launch
     uint64_t n;          // events in this launch
     uint32_t t;          // iteration index
     uint32_t ctr3;       // problem index * 256
     uint32_t key0, key1; // seed
-    int d, N, pstride;
+    int d, N;
     int hrep_log2;       // log2 of the histogram replicas per bin
     int hist;            // 0: no histograms this launch (only S1, S2 are written)
 };
@@ -196,16 +196,24 @@ struct AdjointArgs {
     const void* tab;
     double* partials;    // [gridDim.x][d+1]
     const double* gout;
-    double* grad;        // [d+1]
+    void* grad;          // [d+1], FP64 or (grad_fp32) FP32
     uint64_t n;
     uint32_t t, ctr3, key0, key1;
     int d, N;
+    int grad_fp32;
 };
 
-enum MergeFlags { MERGE_BEGIN = 1, MERGE_END = 2, MERGE_NO_COMBINE = 4, MERGE_REFINE = 8, MERGE_NO_HIST = 16 };
+enum MergeFlags {
+    MERGE_BEGIN = 1,
+    MERGE_END = 2,
+    MERGE_NO_COMBINE = 4,
+    MERGE_REFINE = 8,
+    MERGE_NO_HIST = 16,
+    MERGE_NO_RECORD = 32  // statistics of the iteration kept as the last ones, not recorded
+};
 
 struct MergeArgs {
-    const double* partials;  // [rows][pstride]
+    const double* partials;  // [rows][rstride]: S1, S2 (and H when hslots is null)
     double* hslots;          // [kHistSlots][d*N] histogram accumulators, or null: the rows hold H
     double* acc;             // [2][pstride]
     double* last;            // [pstride]
@@ -219,6 +227,7 @@ struct MergeArgs {
     double alpha;
     double M;                // events of the iteration (at END)
     int rows;
+    int rstride;             // doubles per partial row: 2, or pstride when the rows hold H
     int d, N, pstride, kind;
     int flags;
     int rec_idx;
@@ -287,7 +296,8 @@ hipError_t launch_build_tables(const ProblemPtrs& p, int kind, int d, int N, hip
 hipError_t launch_zero(double* x, size_t n, hipStream_t s);
 hipError_t launch_combine(const double* records, const int32_t* rec_flag, int n_rec, DevResult* result,
                           hipStream_t s);
-hipError_t launch_params_from(const void* src, int n, int is_fp32, double* dst, hipStream_t s);
+hipError_t launch_set_params(int prec, int kind, int d, int N, const void* src, int n, int is_fp32,
+                             const ProblemPtrs& p, hipStream_t s);
 hipError_t launch_reset_results(double* records, int32_t* rec_flag, DevResult* result,
                                 hipStream_t s);
 hipError_t launch_copy_last(const DevResult* result, double* out2, hipStream_t s);

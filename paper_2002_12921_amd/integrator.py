@@ -100,9 +100,11 @@ class Vegas:
 
     # -- the hot path ------------------------------------------------------
     def iterate(self, n_events: int, refine: bool = False, combine: bool = True,
-                chunk: Optional[str] = None, hist: bool = True):
+                chunk: Optional[str] = None, hist: bool = True, record: bool = True):
         """One iteration (or one chunk of one: chunk in {"begin", "mid", "end"}).
-        hist=False skips the histograms (a frozen grid; every chunk alike)."""
+        hist=False skips the histograms (a frozen grid; every chunk alike);
+        record=False keeps the estimate as the last iteration's only (no
+        record slot, not combined)."""
         flags = {None: _lib.ITER_FULL, "begin": _lib.CHUNK_BEGIN, "mid": 0,
                  "end": _lib.CHUNK_END, "begin_end": _lib.ITER_FULL}[chunk]
         if flags & _lib.CHUNK_END:
@@ -110,6 +112,8 @@ class Vegas:
                 flags |= _lib.REFINE
             if not combine:
                 flags |= _lib.NO_COMBINE
+            if not record:
+                flags |= _lib.NO_RECORD
         if not hist:
             flags |= _lib.NO_HIST
         check(lib().vegas_iterate(self._ctx, int(n_events), flags, self._s()), "iterate")
@@ -134,16 +138,34 @@ class Vegas:
                                             1 if params.dtype == torch.float32 else 0, self._s()),
               "set_params_device")
 
+    def get_params_device(self) -> torch.Tensor:
+        """The context's current integrand parameters (FP64, on the device)."""
+        n = self.desc.n_params
+        out = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        check(lib().vegas_get_params_device(self._ctx, ctypes.c_void_p(out.data_ptr()), self._s()),
+              "get_params_device")
+        return out[:n]
+
+    def versions(self) -> tuple[int, int]:
+        """(grid version, parameter version): counters that advance whenever the
+        edges or the integrand parameters change."""
+        g, p = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().vegas_get_versions(self._ctx, ctypes.byref(g), ctypes.byref(p)), "get_versions")
+        return g.value, p.value
+
     def last_iteration_device(self, out: torch.Tensor):
         assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 2
         check(lib().vegas_last_iteration_device(self._ctx, ctypes.c_void_p(out.data_ptr()), self._s()),
               "last_iteration_device")
 
     def adjoint(self, iteration: int, n_events: int, gout: torch.Tensor, grad: torch.Tensor):
+        """grad (d + 1 values, FP64 or FP32) = gout (1/M) sum_e w_e df/d(mu, a)."""
         assert gout.is_cuda and gout.dtype == torch.float64
-        assert grad.is_cuda and grad.dtype == torch.float64 and grad.numel() >= self.dim + 1
+        assert grad.is_cuda and grad.dtype in (torch.float64, torch.float32) and grad.numel() >= self.dim + 1
+        assert grad.is_contiguous()
         check(lib().vegas_adjoint(self._ctx, iteration, n_events, ctypes.c_void_p(gout.data_ptr()),
-                                  ctypes.c_void_p(grad.data_ptr()), self._s()), "adjoint")
+                                  ctypes.c_void_p(grad.data_ptr()), 1 if grad.dtype == torch.float32 else 0,
+                                  self._s()), "adjoint")
 
     # -- inspection ------------------------------------------------------------
     @property

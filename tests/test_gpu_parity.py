@@ -500,6 +500,95 @@ def test_autograd_function(dtype):
     assert gm[0] > 0.3
 
 
+def test_autograd_two_forwards_one_backward():
+    """Two forward passes on one context at different centres, then one
+    backward of their sum: each gradient is the adjoint at its own centre and
+    iteration (the backward sets the forward's parameters back), and the
+    context's parameters afterwards are the last ones set."""
+    from paper_2002_12921_amd.autograd import vegas_integral
+    d, N, M = 4, 40, 100_000
+    mu1_h = np.array([0.15, 0.45, 0.5, 0.62], dtype=np.float32)
+    mu2_h = np.array([0.55, 0.35, 0.42, 0.7], dtype=np.float32)
+    p0 = [float(np.float32(0.1))] + [float(m) for m in mu1_h]
+    v = Vegas(d, N, "gauss", p0, "fp64")
+    for _ in range(3):
+        v.iterate(50_000, refine=True)
+    E = v.edges()
+    a = torch.tensor(0.1, dtype=torch.float32, device="cuda", requires_grad=True)
+    mu1 = torch.tensor(mu1_h, device="cuda", requires_grad=True)
+    mu2 = torch.tensor(mu2_h, device="cuda", requires_grad=True)
+    t1 = v.iteration_index
+    I1 = vegas_integral(mu1, a, v, M)
+    t2 = v.iteration_index
+    I2 = vegas_integral(mu2, a, v, M)
+    assert t2 == t1 + 1
+    (2.0 * I1 + 3.0 * I2).backward()
+    ga = 0.0
+    for mu_t, mu_h, t, wgt in ((mu1, mu1_h, t1, 2.0), (mu2, mu2_h, t2, 3.0)):
+        pr = oracle.Problem(d, N, oracle.GAUSS, [float(np.float32(0.1))] + [float(m) for m in mu_h])
+        G, Gabs = oracle.adjoint(pr, E, t, M)
+        want = wgt * G / M
+        got = mu_t.grad.cpu().numpy().astype(np.float64)
+        # FP32 gradients: one rounding of the FP64 sum
+        assert np.all(np.abs(got - want[:d]) <= 2.0 ** -24 * np.abs(want[:d]) + 1e-12 * wgt * Gabs[:d] / M), (got, want)
+        ga += want[d]
+    assert abs(float(a.grad.cpu()) - ga) <= 1e-6 * abs(ga)
+    # the parameters in force are those of the last forward pass
+    cur = v.get_params_device().cpu().numpy()
+    assert np.array_equal(cur, np.array([np.float32(0.1)] + list(mu2_h), dtype=np.float64))
+    # no record slot was used by the forward passes
+    assert v.result(allow_nonfinite=True)["n_iter"] == 3
+
+
+def test_autograd_backward_after_refine_raises():
+    """A refinement between forward and backward changes the grid the adjoint
+    would use: backward refuses."""
+    from paper_2002_12921_amd.autograd import vegas_integral
+    d = 3
+    v = Vegas(d, 20, "gauss", [0.1] + [0.5] * d, "fp64")
+    v.iterate(20_000, refine=True)
+    mu = torch.full((d,), 0.5, dtype=torch.float64, device="cuda", requires_grad=True)
+    a = torch.tensor(0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+    I = vegas_integral(mu, a, v, 10_000)
+    v.iterate(20_000, refine=True)
+    with pytest.raises(RuntimeError, match="grid changed"):
+        I.backward()
+
+
+def test_autograd_many_forward_passes():
+    """More forward passes than a context has record slots (1024): none of
+    them takes a slot, and a backward after them still matches the oracle."""
+    from paper_2002_12921_amd.autograd import vegas_integral
+    d, N, M = 2, 10, 1000
+    v = Vegas(d, N, "gauss", [0.2, 0.5, 0.5], "fp64")
+    mu = torch.tensor([0.4, 0.6], dtype=torch.float64, device="cuda", requires_grad=True)
+    a = torch.tensor(0.2, dtype=torch.float64, device="cuda", requires_grad=True)
+    for _ in range(1100):
+        I = vegas_integral(mu, a, v, M)
+    t = v.iteration_index - 1
+    I.backward()
+    pr = oracle.Problem(d, N, oracle.GAUSS, [0.2, 0.4, 0.6])
+    S1, _, _ = oracle.accumulate(pr, oracle.uniform_edges(d, N), t, M)
+    assert abs(I.item() - S1 / M) <= 1e-12 * abs(S1 / M)
+    G, Gabs = oracle.adjoint(pr, oracle.uniform_edges(d, N), t, M)
+    assert np.all(np.abs(mu.grad.cpu().numpy() - G[:d] / M) <= 1e-12 * Gabs[:d] / M)
+    # recorded iterations still work after them
+    v.iterate(M)
+    assert v.result()["n_iter"] == 1
+
+
+def test_adjoint_fp32_output_is_rounded_fp64():
+    """The adjoint's FP32 output is the FP64 gradient rounded once."""
+    d, N, M = 5, 30, 200_000
+    v = Vegas(d, N, "gauss", [0.12] + list(np.linspace(0.3, 0.7, d)), "fp32_mixed")
+    gout = torch.full((1,), 1.5, dtype=torch.float64, device="cuda")
+    g64 = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
+    g32 = torch.zeros(d + 1, dtype=torch.float32, device="cuda")
+    v.adjoint(2, M, gout, g64)
+    v.adjoint(2, M, gout, g32)
+    assert np.array_equal(g32.cpu().numpy(), g64.cpu().numpy().astype(np.float32))
+
+
 def test_adjoint_c4_shape():
     """Differentiable case at full size: d = 8, mu ~ U[0.3, 0.7] (seed 0) and
     a = 0.1 as FP32 parameters, grid from 5 FP64 adaptation iterations of 1e6
