@@ -118,6 +118,21 @@ vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes);
 vegas_status vegas_init_grid(vegas_ctx** out, const vegas_desc* desc, void* dev_ws,
                              size_t ws_bytes, vegas_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * vegas_init_grid, but the context's workspace is a static device array of
+ * the library (4 MiB, enough for every admissible dim and n_bins; larger
+ * needs give VEGAS_EUNSUPPORTED) and the host context is a static one, so the
+ * call allocates no device, pinned or host memory.  Built-in integrands only
+ * (VEGAS_USER: EUNSUPPORTED).  There is ONE such context per device (devices
+ * 0..15): a new call on the device re-initialises it in place and returns the
+ * same handle, so the previous handle's state is gone; calls that overlap on
+ * one device, or work still running on the array from another stream, race.
+ * Every other entry point works on the handle as on any context (copies to
+ * the host go straight to the caller's memory, there being no pinned staging
+ * buffer); vegas_destroy on it does nothing. */
+vegas_status vegas_init_grid_noalloc(vegas_ctx** out, const vegas_desc* desc, vegas_stream_t stream);
+
 /* User integrands: the paper's route for integrands written in C, C++ or GPU
  * code outside the framework (sec. 2.3), here as device source compiled at run
  * time for gfx950 with hipRTC.  `source` is HIP device code that defines

@@ -23,7 +23,7 @@ CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST, NO_RECORD = 1, 2
 
 # every symbol include/vegas.h declares
 EXPORTS = [
-    "vegas_workspace_size", "vegas_init_grid", "vegas_init_user", "vegas_user_compile", "vegas_iterate", "vegas_refine", "vegas_result",
+    "vegas_workspace_size", "vegas_init_grid", "vegas_init_grid_noalloc", "vegas_init_user", "vegas_user_compile", "vegas_iterate", "vegas_refine", "vegas_result",
     "vegas_reset_results", "vegas_set_params_device", "vegas_get_params_device", "vegas_get_versions",
     "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "vegas_workspace_size": [P(Desc), P(sz)],
         "vegas_init_grid": [P(vp), P(Desc), vp, sz, vp],
+        "vegas_init_grid_noalloc": [P(vp), P(Desc), vp],
         "vegas_init_user": [P(vp), P(Desc), ctypes.c_char_p, vp, sz, vp],
         "vegas_user_compile": [ctypes.c_char_p, i32, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],

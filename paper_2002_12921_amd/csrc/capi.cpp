@@ -134,6 +134,7 @@ struct vegas_ctx {
     hipModule_t umod = nullptr;
     hipFunction_t usample[2] = {nullptr, nullptr};  // with, without histograms
     hipFunction_t udump = nullptr;
+    bool is_static = false;   // the per-device context of vegas_init_grid_noalloc (never freed)
 };
 
 namespace {
@@ -245,8 +246,15 @@ hipError_t launch_event_kernel(const vegas_ctx* c, const SampleArgs& a, int bloc
                                  unsigned(event_lds(c, 1 << a.hrep_log2, hist)), s, args, nullptr);
 }
 
+// Device-to-host copy through the pinned staging buffer, or (a context
+// without one) straight into the caller's memory.
 vegas_status copy_out(vegas_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t s)
 {
+    if (!c->pinned) {
+        VEGAS_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+        VEGAS_HIP(hipStreamSynchronize(s));
+        return VEGAS_OK;
+    }
     if (bytes > c->pinned_bytes) return fail(VEGAS_EINVAL, "internal: staging buffer too small");
     VEGAS_HIP(hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, s));
     VEGAS_HIP(hipStreamSynchronize(s));
@@ -284,10 +292,13 @@ vegas_status vegas_workspace_size(const vegas_desc* desc, size_t* bytes)
 
 namespace {
 
-// Context creation shared by vegas_init_grid and vegas_init_user (source:
-// the user integrand's code, NULL for the built-in integrands).
+// Context creation shared by vegas_init_grid, vegas_init_user (source: the
+// user integrand's code, NULL for the built-in integrands) and
+// vegas_init_grid_noalloc (into: the device's static context, filled in
+// place; no host or device memory is allocated and there is no pinned
+// staging buffer).
 vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* source, void* dev_ws, size_t ws_bytes,
-                      vegas_stream_t stream)
+                      vegas_stream_t stream, vegas_ctx* into = nullptr)
 {
     if (!out) return fail(VEGAS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -301,8 +312,16 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
     if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0) return fail(VEGAS_EWORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total) return fail(VEGAS_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
-    vegas_ctx* c = new (std::nothrow) vegas_ctx();
-    if (!c) return fail(VEGAS_EINVAL, "out of host memory");
+    vegas_ctx* c = into;
+    if (c) {
+        // reused in place: timing events of an earlier use are released first
+        free_events(c);
+        *c = vegas_ctx();
+        c->is_static = true;
+    } else {
+        c = new (std::nothrow) vegas_ctx();
+        if (!c) return fail(VEGAS_EINVAL, "out of host memory");
+    }
     c->d = desc->dim;
     c->N = desc->n_bins;
     c->kind = desc->integrand;
@@ -318,7 +337,10 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
     auto bail = [&](vegas_status e) {
         if (c->pinned) (void)hipHostFree(c->pinned);
         if (c->umod) (void)hipModuleUnload(c->umod);
-        delete c;
+        if (c->is_static)
+            *c = vegas_ctx();
+        else
+            delete c;
         return e;
     };
     hipError_t he;
@@ -380,10 +402,12 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
         return bail(fail(VEGAS_EUNSUPPORTED, "no launch shape of the event kernel fits dim %d, n_bins %d", c->d, c->N));
     int nb = c->cu_count * per_cu;
     c->blocks_auto = nb > kMaxBlocks ? kMaxBlocks : (nb < 1 ? 1 : nb);
-    c->pinned_bytes = state_bytes(c) + 4096;
-    if ((he = hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
-        c->pinned = nullptr;
-        return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
+    if (!c->is_static) {
+        c->pinned_bytes = state_bytes(c) + 4096;
+        if ((he = hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
+            c->pinned = nullptr;
+            return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
+        }
     }
     const size_t pbytes = sizeof(double) * desc->n_params;
     if ((pbytes > 0 && (he = hipMemcpyAsync(c->P.params, desc->params, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess) ||
@@ -396,6 +420,21 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
 }
 
 }  // namespace
+
+namespace vegas {
+
+// The host half of vegas_init_grid_noalloc: a context per device, kept for the
+// life of the process, over the static device workspace ws of ws_bytes.
+vegas_status init_static_ctx(vegas_ctx** out, const vegas_desc* desc, int device, void* ws, size_t ws_bytes,
+                             vegas_stream_t stream)
+{
+    static vegas_ctx g_static[kStaticDevices];
+    if (device < 0 || device >= kStaticDevices)
+        return fail(VEGAS_EUNSUPPORTED, "device %d: the static contexts cover devices 0..%d", device, kStaticDevices - 1);
+    return init_ctx(out, desc, nullptr, ws, ws_bytes, stream, &g_static[device]);
+}
+
+}  // namespace vegas
 
 extern "C" {
 
@@ -680,6 +719,13 @@ vegas_status vegas_get_iteration(vegas_ctx* c, double* sums, double* hist, vegas
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (c->rec_idx == 0 && !c->has_hist) return fail(VEGAS_ESTATE, "no completed iteration");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!c->pinned) {
+        if (sums) VEGAS_HIP(hipMemcpyAsync(sums, c->P.last, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (hist)
+            VEGAS_HIP(hipMemcpyAsync(hist, c->P.last + 2, sizeof(double) * c->d * c->N, hipMemcpyDeviceToHost, s));
+        VEGAS_HIP(hipStreamSynchronize(s));
+        return VEGAS_OK;
+    }
     const size_t bytes = sizeof(double) * c->L.pstride;
     if (bytes > c->pinned_bytes) return fail(VEGAS_EINVAL, "internal: staging buffer too small");
     VEGAS_HIP(hipMemcpyAsync(c->pinned, c->P.last, bytes, hipMemcpyDeviceToHost, s));
@@ -703,7 +749,8 @@ vegas_status vegas_get_state(vegas_ctx* c, void* host_buf, size_t bytes, vegas_s
     if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
     if (bytes < state_bytes(c)) return fail(VEGAS_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, state_bytes(c));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    char* p = static_cast<char*>(c->pinned);
+    // staged through the pinned buffer, or copied straight into host_buf
+    char* p = c->pinned ? static_cast<char*>(c->pinned) : static_cast<char*>(host_buf);
     StateHeader h{kStateMagic, 1u, c->d, c->N, c->kind, c->prec, c->t, c->rec_idx, c->has_hist ? 1 : 0, c->seed};
     std::memcpy(p, &h, sizeof(h));
     size_t o = sizeof(h);
@@ -721,7 +768,7 @@ vegas_status vegas_get_state(vegas_ctx* c, void* host_buf, size_t bytes, vegas_s
     VEGAS_HIP(hipMemcpyAsync(p + o, c->P.last, lb, hipMemcpyDeviceToHost, s));
     o += lb;
     VEGAS_HIP(hipStreamSynchronize(s));
-    std::memcpy(host_buf, p, o);
+    if (p != host_buf) std::memcpy(host_buf, p, o);
     return VEGAS_OK;
 }
 
@@ -846,6 +893,7 @@ vegas_status vegas_timing_read(vegas_ctx* c, double* sample_ms, double* merge_ms
 vegas_status vegas_destroy(vegas_ctx* c)
 {
     if (!c) return VEGAS_OK;
+    if (c->is_static) return VEGAS_OK;  // the device's static context lives on
     free_events(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->umod) (void)hipModuleUnload(c->umod);

@@ -18,6 +18,14 @@ int expected_params(int kind, int d);
 // Full validation of a problem description (no HIP call).
 vegas_status check_desc(const vegas_desc* d);
 
+// Devices that can hold a static (allocation-free) context.
+constexpr int kStaticDevices = 16;
+
+// The device's static context of vegas_init_grid_noalloc, (re)initialised
+// over the static device workspace ws (ws_bytes); allocates nothing.
+vegas_status init_static_ctx(vegas_ctx** out, const vegas_desc* desc, int device, void* ws, size_t ws_bytes,
+                             vegas_stream_t stream);
+
 }  // namespace vegas
 
 #define VEGAS_HIP(expr)                                                                               \

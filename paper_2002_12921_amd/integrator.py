@@ -53,12 +53,17 @@ class Vegas:
     ``__device__ vegas_real vegas_integrand(const vegas_real* x, int dim, const double* params)``
     (a user integrand, compiled at run time; vegas_real is double for
     precision "fp64" and float for "fp32_mixed"; integrand then defaults to
-    "user" and params to none)."""
+    "user" and params to none).
+
+    static_workspace: use the device's one static context
+    (vegas_init_grid_noalloc: no allocation; a later static Vegas on the same
+    device takes it over)."""
 
     def __init__(self, dim: int, n_bins: int = 50, integrand=None,
                  params: Optional[Sequence[float]] = None, precision="fp64", seed: int = 0,
                  alpha: float = 1.5, problem: int = 0, device=None,
-                 stream: Optional[torch.cuda.Stream] = None, source: Optional[str] = None):
+                 stream: Optional[torch.cuda.Stream] = None, source: Optional[str] = None,
+                 static_workspace: bool = False):
         if integrand is None:
             integrand = "user" if source is not None else "gauss"
         if params is None:
@@ -69,6 +74,15 @@ class Vegas:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
         L = lib()
+        if static_workspace:
+            if source is not None:
+                raise ValueError("user integrands need their own workspace")
+            self.ws = None
+            self._ctx = ctypes.c_void_p()
+            with torch.cuda.device(self.device):
+                check(L.vegas_init_grid_noalloc(ctypes.byref(self._ctx), ctypes.byref(self.desc), self._s()),
+                      "init_grid_noalloc")
+            return
         nbytes = ctypes.c_size_t()
         check(L.vegas_workspace_size(ctypes.byref(self.desc), ctypes.byref(nbytes)), "workspace_size")
         with torch.cuda.device(self.device):

@@ -193,3 +193,35 @@ def test_user_desc_checks():
     n_ev = (ctypes.c_int64 * 1)(1000)
     nb = ctypes.c_size_t()
     assert L.vegas_batch_workspace_size(ctypes.byref(u), n_ev, 1, ctypes.byref(nb)) == _lib.VEGAS_EUNSUPPORTED
+
+
+def test_noalloc_rejects_before_hip():
+    """The allocation-free init validates before any HIP call: NULL out, a bad
+    description, and user integrands (which are compiled and loaded at init)."""
+    L = _lib.lib()
+    d, keep = make_desc(4, 50, "gauss", [0.1] + [0.5] * 4)
+    assert L.vegas_init_grid_noalloc(None, ctypes.byref(d), None) == _lib.VEGAS_EINVAL
+    ctx = ctypes.c_void_p()
+    bad, keep2 = make_desc(4, 50, "gauss", [0.1] + [0.5] * 3)
+    assert L.vegas_init_grid_noalloc(ctypes.byref(ctx), ctypes.byref(bad), None) == _lib.VEGAS_EINVAL
+    u, keep3 = make_desc(4, 50, "user", [], "fp64")
+    assert L.vegas_init_grid_noalloc(ctypes.byref(ctx), ctypes.byref(u), None) == _lib.VEGAS_EUNSUPPORTED
+    assert ctx.value is None
+
+
+def test_static_workspace_covers_every_admissible_size():
+    """Every (dim, n_bins) the library admits needs at most the 4 MiB static
+    workspace of the allocation-free context (FP64 and FP32 tables, one- and
+    two-centre integrands)."""
+    L = _lib.lib()
+    worst = 0
+    for prec in ("fp64", "fp32_mixed"):
+        for kind, pf in (("gauss", lambda d: [0.1] + [0.5] * d),
+                         ("bimodal", lambda d: [0.1] + [0.3] * d + [0.6] * d)):
+            for d in range(1, 65):
+                for N in range(2, 256, 3):
+                    desc, keep = make_desc(d, N, kind, pf(d), prec)
+                    n = ctypes.c_size_t()
+                    if L.vegas_workspace_size(ctypes.byref(desc), ctypes.byref(n)) == _lib.VEGAS_OK:
+                        worst = max(worst, n.value)
+    assert 0 < worst <= 4 << 20
