@@ -37,7 +37,7 @@ int dmax_of(int d)
 // Byte layout of a batch workspace.
 struct BatchLayout {
     size_t probs, items, queue, params, cst, records, rec_flag, results;
-    std::vector<size_t> edges, tab64, tab32, last;  // per problem
+    std::vector<size_t> edges, tab64, tab32, thr, last;  // per problem
     size_t partials;
     size_t total;
     size_t max_items;
@@ -70,6 +70,7 @@ BatchLayout batch_layout(const vegas_desc* descs, const int64_t* n_events, int n
         L.edges.push_back(take(sizeof(double) * d * (N + 1)));
         L.tab64.push_back(take(sizeof(double) * 2 * d * N));
         L.tab32.push_back(take(sizeof(float) * 4 * d * N));
+        L.thr.push_back(take(sizeof(uint64_t) * d));
         L.last.push_back(take(sizeof(double) * (2 + d * N)));
     }
     L.partials = take(sizeof(double) * pd);
@@ -305,7 +306,9 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         for (int th : {1024, 512}) {
             for (int l2 = 4; l2 >= 0; --l2) {
                 const size_t lds = lds_for(1 << l2);
-                if (lds + 256 > kLdsLimit) continue;
+                // 256: the kernel's static LDS (work item, wave partials), and
+                // the discontinuous integrand's thresholds
+                if (lds + 256 + (b->kind == VEGAS_GENZ_DISC ? sizeof(uint64_t) * dm : 0) > kLdsLimit) continue;
                 const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th);
                 const double score = double(bpc * th / 64) * kRepFactor[l2];
                 if (score > best + 1e-9) {
@@ -339,6 +342,7 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         pr.edges = reinterpret_cast<double*>(b->at(L.edges[p]));
         pr.tab64 = reinterpret_cast<double2*>(b->at(L.tab64[p]));
         pr.tab32 = reinterpret_cast<float*>(b->at(L.tab32[p]));
+        pr.thr = reinterpret_cast<uint64_t*>(b->at(L.thr[p]));
         pr.last = reinterpret_cast<double*>(b->at(L.last[p]));
         pr.records = reinterpret_cast<double*>(b->at(L.records)) + size_t(p) * 2 * kBatchMaxIter;
         pr.rec_flag = reinterpret_cast<int32_t*>(b->at(L.rec_flag)) + size_t(p) * kBatchMaxIter;

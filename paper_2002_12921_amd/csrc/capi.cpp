@@ -193,6 +193,7 @@ SampleArgs sample_args(const vegas_ctx* c, int64_t e0, int64_t n, bool no_hist)
     SampleArgs a{};
     a.cst = c->P.cst;
     a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.thr = c->P.thr;
     a.partials = c->P.partials;
     a.hslots = c->P.hslots;
     a.e0 = uint64_t(e0);
@@ -218,6 +219,7 @@ MergeArgs merge_args(const vegas_ctx* c, int rows, int flags, double M)
     a.edges = c->P.edges;
     a.tab64 = c->P.tab64;
     a.tab32 = c->P.tab32;
+    a.thr = c->P.thr;
     a.cst = c->P.cst;
     a.records = c->P.records;
     a.rec_flag = c->P.rec_flag;
@@ -672,6 +674,7 @@ vegas_status vegas_dump_events(vegas_ctx* c, int64_t iteration, int64_t first, i
     DumpArgs a{};
     a.cst = c->P.cst;
     a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);
+    a.thr = c->P.thr;
     a.out = dev_out;
     a.e0 = uint64_t(first);
     a.n = uint64_t(count);

@@ -186,8 +186,8 @@ struct EventEval {
     int fe;           // FP32: binary exponent of the integrand (f ~ 2^fe F)
 
     __device__ __forceinline__ void run(const EvalConsts<P, KIND, DMAX>& c, const tab_t* __restrict__ tab,
-                                        uint64_t e, uint32_t t, uint32_t ctr3, uint32_t key0,
-                                        uint32_t key1, int d_rt, int N)
+                                        const uint64_t* __restrict__ thr, uint64_t e, uint32_t t,
+                                        uint32_t ctr3, uint32_t key0, uint32_t key1, int d_rt, int N)
     {
         // every fused multiply-add here is an explicit fma(): nothing else is
         // contracted, so all kernel variants round the same way
@@ -252,7 +252,11 @@ struct EventEval {
                                 qb = fma(q_t(ubi), q_t(ubi), qb);
                             }
                         } else if constexpr (KIND == GENZ_DISC) {
-                            inside = inside && (ui > real(0));
+                            // x_i > a_i as the FP64 x decides it: one integer
+                            // comparison of b 2^32 + lo with the dimension's
+                            // threshold (disc_threshold), in both precisions
+                            const uint64_t Pw = (uint64_t(uint32_t(bi)) << 32) | lo;
+                            inside = inside && (Pw >= thr[i]);
                             if constexpr (P::is64)
                                 sa = fma(c.p1[i], ui, sa);
                             else if constexpr (kQ32)

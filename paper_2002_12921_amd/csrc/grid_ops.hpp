@@ -65,10 +65,48 @@ __device__ __forceinline__ void write_table_entry(int i, int b, double lo, doubl
     write_table_entry(i, b, lo, hi, c->cA64[i], c->cB64[i], c->dscale32, kind, N, tab64, tab32);
 }
 
+// The discontinuous integrand (Eq. genzdisc) is zero unless x_i > a_i in
+// every dimension, a decision the method takes on x = E_b + delta (E_{b+1} -
+// E_b) in FP64.  The event's bin and position come from the 64-bit integer
+// P = b 2^32 + lo (delta = (lo + h)/2^32, see bin_words), and x, evaluated
+// in that order in FP64, never decreases as P grows: within a bin every
+// operation is monotone, and the largest delta, 1 - 2^-33, keeps the exact
+// value below E_{b+1} by more than the two roundings can add, so no x of a
+// bin exceeds the next bin's lower edge.  Hence x > a holds exactly when
+// P >= T for the smallest such P, which is found here once per grid (a
+// bisection over lo in the bin that holds a), and the event kernels, FP64
+// and FP32 alike, decide with one integer comparison what the FP64 x would.
+// The threshold within bin b (edges Eb <= a < Eb1) of a grid of N bins.
+__device__ static uint64_t disc_bin_threshold(double Eb, double Eb1, int b, int N, double a)
+{
+#pragma clang fp contract(off)
+    const double w = Eb1 - Eb;
+    const double h = (N & 1) ? 0.5 : 0.0;
+    uint64_t lo = 0, hi = uint64_t(1) << 32;  // hi: no event of bin b lies above a
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        const double x = Eb + ((double(mid) + h) * 0x1p-32) * w;
+        if (x > a)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return (uint64_t(b) << 32) + lo;
+}
+
+__device__ static uint64_t disc_threshold(const double* E, int N, double a)
+{
+    int b = 0;  // the bin holding a: the last b with E_b <= a (E_0 = 0 <= a < 1 = E_N)
+    for (int k = 1; k < N; ++k)
+        if (E[k] <= a) b = k;
+    return disc_bin_threshold(E[b], E[b + 1], b, N, a);
+}
+
 __device__ static void write_tables(int i, const double* E, const DevConst* __restrict__ c, int kind,
-                                    int N, double2* tab64, float* tab32)
+                                    int N, double2* tab64, float* tab32, uint64_t* thr)
 {
     for (int b = threadIdx.x; b < N; b += blockDim.x) write_table_entry(i, b, E[b], E[b + 1], c, kind, N, tab64, tab32);
+    if (kind == GENZ_DISC && threadIdx.x == 0) thr[i] = disc_threshold(E, N, c->cA64[i]);
 }
 
 // Scale of the FP32 table's widths: 2^-ws with ws = round(log2 N), so the
@@ -203,7 +241,7 @@ __device__ static void refine_dim(const MergeArgs& a, int i, const double* h, co
         E[k] = e;
     }
     __syncthreads();
-    write_tables(i, En, a.cst, a.kind, N, a.tab64, a.tab32);
+    write_tables(i, En, a.cst, a.kind, N, a.tab64, a.tab32, a.thr);
 }
 
 // The same refinement for N <= 64 by one wave (lane b holds bin b's value hb
@@ -252,10 +290,15 @@ __device__ static void refine_dim_wave(const MergeArgs& a, int i, double hb, dou
     // tables of bin b: lower edge (new edge b, or the fixed E_0), upper edge
     // (new edge b + 1 from the next lane, or the fixed E_N)
     const double up = __shfl_down(e, 1, 64);
-    if (in) {
-        const double lo = b == 0 ? Eb : e;
-        const double hi = b == N - 1 ? Eb1 : up;
-        write_table_entry(i, b, lo, hi, a.cst, a.kind, N, a.tab64, a.tab32);
+    const double lo = b == 0 ? Eb : e;
+    const double hi = b == N - 1 ? Eb1 : up;
+    if (in) write_table_entry(i, b, lo, hi, a.cst, a.kind, N, a.tab64, a.tab32);
+    if (a.kind == GENZ_DISC) {
+        // the bin holding a_i is the count of interior edges at or below it
+        const double th = a.cst->cA64[i];
+        const int bth = __popcll(__ballot(b >= 1 && b <= N - 1 && e <= th));
+        const double El = __shfl(lo, bth, 64), Eu = __shfl(hi, bth, 64);
+        if (b == 0) a.thr[i] = disc_bin_threshold(El, Eu, bth, N, th);
     }
 }
 

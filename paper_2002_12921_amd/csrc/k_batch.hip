@@ -30,6 +30,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
     extern __shared__ __align__(128) unsigned char smem[];
     __shared__ int s_item;
     __shared__ double red[kBlock / 64];
+    __shared__ uint64_t thr[KIND == GENZ_DISC ? DMAX : 1];  // x_i > a_i thresholds of the problem
     // histogram [dim][bin][replica], lane l adding into replica l mod rep
     const int rl2 = a.hrep_log2, rep = 1 << rl2;
     const int lrep = int(threadIdx.x) & (rep - 1);
@@ -58,6 +59,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
             for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
+            if constexpr (KIND == GENZ_DISC)
+                for (int k = threadIdx.x; k < d; k += blockDim.x) thr[k] = pr.thr[k];
             hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
         }
         if constexpr (HIST)
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         int ng = 0;
         for (uint64_t k = threadIdx.x; k < it.n; k += blockDim.x) {
             EventEval<P, KIND, DMAX> ev;
-            ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
+            ev.run(cst, tab, thr, it.e0 + k, a.t, ctr3, key0, key1, d, N);
             double v, v2;
             {
                 // rounded as written in every variant (with or without histograms)
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_batch_finish(BatchArgs a, int
     m.edges = pr.edges;
     m.tab64 = pr.tab64;
     m.tab32 = pr.tab32;
+    m.thr = pr.thr;
     m.cst = pr.cst;
     m.records = pr.records;
     m.rec_flag = pr.rec_flag;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_batch_reset(BatchArgs a, int 
         double* E = pr.edges + size_t(g) * (pr.N + 1);
         for (int k = threadIdx.x; k <= pr.N; k += blockDim.x) E[k] = double(k) / double(pr.N);
         __syncthreads();
-        write_tables(g, E, pr.cst, kind, pr.N, pr.tab64, pr.tab32);
+        write_tables(g, E, pr.cst, kind, pr.N, pr.tab64, pr.tab32, pr.thr);
     } else if (g == pr.d) {
         for (int k = threadIdx.x; k < pr.pstride; k += blockDim.x) pr.last[k] = 0.0;
         for (int k = threadIdx.x; k < 2 * n_rec; k += blockDim.x) pr.records[k] = 0.0;

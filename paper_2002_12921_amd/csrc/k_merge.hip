@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void k_set_params(int prec, int kind, int d, i
     const double* E = p.edges + size_t(i) * (N + 1);
     for (int b = threadIdx.x; b < N; b += blockDim.x)
         write_table_entry(i, b, E[b], E[b + 1], cA, cB, ds, kind, N, p.tab64, p.tab32);
+    if (kind == GENZ_DISC && threadIdx.x == 0) p.thr[i] = disc_threshold(E, N, cA);
 }
 
 // Uniform grid E_k = k/N and a clean state (tables: k_build_tables).
@@ -155,7 +156,7 @@ __global__ void k_zero(double* x, size_t n)
 __global__ void k_build_tables(ProblemPtrs p, int kind, int N)
 {
     const int i = blockIdx.x;
-    write_tables(i, p.edges + size_t(i) * (N + 1), p.cst, kind, N, p.tab64, p.tab32);
+    write_tables(i, p.edges + size_t(i) * (N + 1), p.cst, kind, N, p.tab64, p.tab32, p.thr);
 }
 
 __global__ void k_combine(const double* records, const int32_t* rec_flag, int n_rec, DevResult* R)

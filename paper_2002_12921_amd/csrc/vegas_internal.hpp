@@ -75,6 +75,7 @@ struct Layout {
     size_t edges;     // double[d][N+1]
     size_t tab64;     // double2[d][N]  (E_b, E_{b+1}-E_b)
     size_t tab32;     // float2 or float4 [d][N]  (offsets from the centres, scaled width)
+    size_t thr;       // uint64[d]  Genz discontinuous: x_i > a_i as an integer threshold
     size_t partials;  // double[kMaxBlocks][2]  per-block (S1, S2) of the event kernel
     size_t hslots;    // double[kHistSlots][d*N]  histogram accumulators of the event kernel
     size_t acc;       // double[2][pstride]   chunk accumulators (hi, lo)
@@ -100,6 +101,7 @@ inline Layout make_layout(int d, int N)
     L.edges = take(sizeof(double) * d * (N + 1));
     L.tab64 = take(sizeof(double) * 2 * d * N);
     L.tab32 = take(sizeof(float) * 4 * d * N);
+    L.thr = take(sizeof(uint64_t) * d);
     L.partials = take(sizeof(double) * size_t(kMaxBlocks) * 2);
     L.hslots = take(sizeof(double) * size_t(kHistSlots) * d * N);
     L.acc = take(sizeof(double) * 2 * size_t(ps));
@@ -134,6 +136,7 @@ struct ProblemPtrs {
     double* edges;
     double2* tab64;
     float* tab32;
+    uint64_t* thr;
     double* partials;
     double* hslots;
     double* acc;
@@ -153,6 +156,7 @@ inline ProblemPtrs problem_ptrs(void* ws, const Layout& L)
     p.edges = reinterpret_cast<double*>(b + L.edges);
     p.tab64 = reinterpret_cast<double2*>(b + L.tab64);
     p.tab32 = reinterpret_cast<float*>(b + L.tab32);
+    p.thr = reinterpret_cast<uint64_t*>(b + L.thr);
     p.partials = reinterpret_cast<double*>(b + L.partials);
     p.hslots = reinterpret_cast<double*>(b + L.hslots);
     p.acc = reinterpret_cast<double*>(b + L.acc);
@@ -170,6 +174,7 @@ inline ProblemPtrs problem_ptrs(void* ws, const Layout& L)
 struct SampleArgs {
     const DevConst* cst;
     const void* tab;     // double2* (FP64) or float2* (FP32), [d][N]
+    const uint64_t* thr; // [d] Genz discontinuous thresholds
     double* partials;    // [gridDim.x][2]: S1, S2 (the histogram goes to hslots)
     double* hslots;      // [kHistSlots][d*N]: block b adds its histogram into slot (b / 8) mod kHistSlots
     uint64_t e0;         // first event index of this launch
@@ -185,6 +190,7 @@ struct SampleArgs {
 struct DumpArgs {
     const DevConst* cst;
     const void* tab;
+    const uint64_t* thr;
     double* out;         // [n][3d+2]
     uint64_t e0, n;
     uint32_t t, ctr3, key0, key1;
@@ -220,6 +226,7 @@ struct MergeArgs {
     double* edges;           // [d][N+1]
     double2* tab64;
     float* tab32;
+    uint64_t* thr;           // Genz discontinuous thresholds (rebuilt with the tables)
     const DevConst* cst;     // centres for the FP32 table
     double* records;
     int32_t* rec_flag;
@@ -242,6 +249,7 @@ struct BatchProblem {
     double* edges;
     double2* tab64;
     float* tab32;
+    uint64_t* thr;
     double* last;       // S1, S2, H of the last iteration
     double* records;    // [n_iter][2]
     int32_t* rec_flag;
