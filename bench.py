@@ -30,6 +30,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# worker processes of the CPU baseline (at most; the host's cores otherwise)
+CPU_WORKERS = 12
 METRIC = "events/s per Vegas iteration (d=8 Gaussian, 1e7 evts), FP32-mixed vs FP64"
 D, NBINS, A, ALPHA, EVENTS = 8, 50, 0.1, 1.5, 10_000_000
 
@@ -40,25 +42,24 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
 def alg_slots_per_event(d: int) -> int:
-    """VALU lane-slots per event that the FP32-mixed Gaussian event kernel's
-    algorithm needs (d <= 8), each VALU instruction one slot -- the
-    32x32->64 multiply-add included, which issues at full rate on gfx950:
-      Philox4x32-10: ceil(d/4) blocks x 10 rounds x (2 multiply-adds + 2
-        three-way xors), less one multiply per extra block (the first round's
-        product of counter word 0 is common to all blocks of an event)
-                                                   = 40 ceil(d/4) - (ceil(d/4) - 1)
-      per dimension: bin and low word (1 multiply-add), convert (1), table
-        address (1), scaled map (1 fma), Jacobian product (1), exponent term
-        (1 fma), histogram address (1)              = 7 d
-      per event: exponent split and exponential (convert, scale, floor,
-        subtract, convert, exp2: 6), value (F w, convert, exponent add,
-        ldexp, times C: 5), v^2 and the two grouped sums with their
-        compensation (4), lane replica offset and loop (5)     = 20
-    The LDS reads and atomics run on the LDS pipe and are not counted.  For
-    d = 8 the count equals the VALU instructions the kernel executes per
-    event (the counters read 155.4)."""
-    g = math.ceil(d / 4)
-    return 40 * g - (g - 1) + 7 * d + 20
+    """VALU issue slots per event that the method needs for the Gaussian at
+    dimension d, from a fixed table of its steps (written from the method,
+    not read from this kernel's instruction counts, so a wasteful kernel
+    cannot raise its own ceiling):
+      Philox4x32-10: ceil(d/4) calls x 10 rounds x (2 wide multiplies
+        + 2 XORs)                                            40 ceil(d/4)
+      binning: per dimension 1 wide multiply-add + 1 integer op       2d
+      map: per dimension convert + fma + table address                3d
+      integrand: per dimension subtract + fma, 3 more, and one
+        exponential at 4 slots (a quarter-rate transcendental)    2d + 7
+      Jacobian: per dimension 1 multiply                               d
+      sums: convert, square and two compensated updates               10
+      histograms: per dimension 1 address                              d
+    = 40 ceil(d/4) + 9d + 17, 169 at d = 8.  The table reads and histogram
+    atomics run on the LDS pipe and are not counted.  Every VALU instruction
+    is one slot except the exponential; the 32x32->64 multiply-add issues at
+    the full rate on gfx950 (bench.py --issue-probe measures both)."""
+    return 40 * math.ceil(d / 4) + 9 * d + 17
 
 
 # Counter summary of the event kernel (HBM bytes per launch from FETCH_SIZE and
@@ -76,18 +77,21 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, note): the counter-derived HBM traffic of the event
-    kernel, or None when there is no summary or the kernel changed since."""
+def measured_counters():
+    """(bytes per launch, VALU busy, note): the counter-derived HBM traffic of
+    the event kernel and the share of its SIMD cycles that issued VALU
+    instructions, or Nones when there is no summary or the kernel changed
+    since the counters were taken."""
     try:
         with open(PMC_SUMMARY) as fh:
             text = fh.read()
     except OSError:
-        return None, "no counter summary"
+        return None, None, "no counter summary"
     vals = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
     if vals.get("kernel_source_sha256") != kernel_source_digest():
-        return None, "kernel changed since the counters were taken"
-    return float(vals["traffic_bytes_per_launch"]), (
+        return None, None, "kernel changed since the counters were taken"
+    busy = float(vals["valu_busy"]) if "valu_busy" in vals else None
+    return float(vals["traffic_bytes_per_launch"]), busy, (
         f"FETCH_SIZE x {vals['fetch_scale']} + WRITE_SIZE x {vals['write_scale']} (copy-calibrated), "
         f"{os.path.relpath(PMC_SUMMARY, ROOT)}")
 
@@ -169,7 +173,14 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     v.timing_enable(False)
     # the event kernel alone: `steps` launches back to back between two events
     kernel_ms = v.time_event_kernel(EVENTS, steps)
+    # one more adaptation step, kept for the comparison with the oracle
+    E_before = v.edges()
+    t = v.iteration_index
+    v.iterate(EVENTS, refine=True, combine=False)
+    S1, S2, H = v.last_iteration()
+    lockstep = {"t": t, "edges": E_before, "edges_after": v.edges(), "S1": S1, "S2": S2, "H": H}
     return {
+        "lockstep": lockstep,
         "ms_per_step": total_ms / steps,
         "wall_ms_per_step": wall * 1e3 / steps,
         "events_per_s": _events_per_s(total_ms / steps),
@@ -255,7 +266,9 @@ def batch_c5(reps: int):
     probs = workloads.batch256()
     n_iter, n_adapt = 10, 5
     total = n_iter * sum(q["n_events"] for q in probs)
+    t0 = time.perf_counter()
     b = VegasBatch(probs, n_iter, n_adapt)
+    plan_s = time.perf_counter() - t0
     b.run()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -283,6 +296,7 @@ def batch_c5(reps: int):
     seq_ms = start.elapsed_time(stop)
     return {"events_per_s": total / (ms * 1e-3), "ms_per_run": ms, "events_per_run": total,
             "tile_events": sched["tile_events"], "blocks": sched["blocks"], "n_items": sched["n_items"],
+            "buckets": sched["buckets"], "tuned_ms": sched["tuned_ms"], "plan_s": plan_s,
             "sequential_ms": seq_ms, "batch_over_sequential": seq_ms / ms,
             "finite_results": int(sum(1 for r in res if math.isfinite(r["integral"])))}
 
@@ -463,21 +477,113 @@ def phase_split(steps: int):
     return out
 
 
-def cpu_baseline(iters: int):
-    """The FP64 oracle (single-threaded C, as it stands) on the same workload:
-    `iters` iterations of 1e7 events with refinement, seed 0."""
+def _oracle_chunk(args):
+    """Worker of the CPU baseline: the oracle's sums over one contiguous range
+    of events of one iteration (the oracle as it stands, one call)."""
+    import numpy as np
     import oracle
-    pr = oracle.Problem(D, NBINS, oracle.GAUSS, [A] + [0.5] * D, seed=0, alpha=ALPHA)
+    params, E, t, e0, n = args
+    pr = oracle.Problem(D, NBINS, oracle.GAUSS, params, seed=0, alpha=ALPHA)
+    return oracle.accumulate(pr, np.asarray(E), t, n, e0)
+
+
+def _oracle_iteration(pool, workers: int, params, E, t: int, n: int):
+    """The oracle's (S1, S2, H) of one iteration, its events split into one
+    contiguous range per worker process; the ranges' sums are added in
+    order (S1, S2 with math.fsum)."""
+    import numpy as np
+    step = -(-n // workers)
+    jobs = [(params, E.tolist(), t, e0, min(step, n - e0)) for e0 in range(0, n, step)]
+    parts = pool.map(_oracle_chunk, jobs)
+    S1 = math.fsum(p[0] for p in parts)
+    S2 = math.fsum(p[1] for p in parts)
+    H = np.sum(np.stack([p[2] for p in parts]), axis=0)
+    return S1, S2, H
+
+
+def cpu_baseline(pool, workers: int, iters: int, lockstep: dict):
+    """The FP64 oracle (plain C, as it stands) on the same workload, on the
+    host's cores: `iters` adaptation iterations of 1e7 events with
+    refinement, seed 0, each iteration's events split over `workers`
+    processes.  Also the error of each GPU path against the oracle on one
+    adaptation iteration of the benchmark, run in lockstep on the path's own
+    grid (the same points): |dS1|/S1, |dS2|/S2, the largest histogram
+    difference over its dimension's total, and the refined grid against the
+    oracle's refinement of the path's histograms."""
+    import numpy as np
+    import oracle
+    params = [A] + [0.5] * D
     E = oracle.uniform_edges(D, NBINS)
-    n_events = EVENTS
+    _oracle_iteration(pool, workers, params, E, 0, 2 * workers)  # workers load the oracle
     t0 = time.perf_counter()
     for t in range(iters):
-        S1, S2, H = oracle.accumulate(pr, E, t, n_events)
+        S1, S2, H = _oracle_iteration(pool, workers, params, E, t, EVENTS)
         E = oracle.refine(H, E, ALPHA)
     dt = time.perf_counter() - t0
-    return {"value": iters * n_events / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations x {n_events:.0e} events of the d=8 workload "
-                      f"(accumulate + refine), FP64, single thread, {dt:.1f} s"}
+    errors = {}
+    for prec, rec in lockstep.items():
+        o1, o2, Ho = _oracle_iteration(pool, workers, params, rec["edges"], rec["t"], EVENTS)
+        tot = Ho.sum(axis=1, keepdims=True)
+        errors[prec] = {
+            "iteration": rec["t"],
+            "S1_rel": abs(rec["S1"] - o1) / abs(o1),
+            "S2_rel": abs(rec["S2"] - o2) / abs(o2),
+            "hist_max_rel_to_dim_total": float(np.max(np.abs(rec["H"] - Ho) / tot)),
+            "refined_edges_max_abs": float(np.max(np.abs(rec["edges_after"] -
+                                                         oracle.refine(rec["H"], rec["edges"], ALPHA)))),
+        }
+        # I_t = S1/M (relative error that of S1) and its error sigma_t
+        sg = math.sqrt(oracle.iteration_stats(rec["S1"], rec["S2"], EVENTS)[1])
+        so = math.sqrt(oracle.iteration_stats(o1, o2, EVENTS)[1])
+        errors[prec]["sigma_t_rel"] = abs(sg - so) / so
+    affinity = len(os.sched_getaffinity(0))
+    return {"value": iters * EVENTS / dt, "unit": "events/s", "cores": workers, "kind": "oracle",
+            "host_cores_available": affinity,
+            "sample": f"{iters} iterations x {EVENTS:.0e} events of the d=8 workload (accumulate + refine), "
+                      f"FP64, each iteration's events split over {workers} processes, {dt:.1f} s",
+            "error_vs_oracle": errors}
+
+
+# VALU instructions per step of each issue-probe kernel's loop (eight chains;
+# counted in the gfx950 code this build emits), and the 64-bit multiply-adds
+# among them: mad: 8 v_mad_u64_u32 + 8 v_bitop3_b32 + 8 v_mov_b32; xor:
+# 16 v_bitop3_b32; fma: 8 v_fma_f32; exp: 8 v_exp_f32.
+PROBE_KERNELS = (("mad_bitop3", 24), ("bitop3", 16), ("fma_f32", 8), ("exp_f32", 8))
+PROBE_ITERS = 32768
+
+
+def issue_probe():
+    """Issue rates of the instruction classes the VALU bound weighs
+    (vegas_probe_issue_rates): lane-instructions per second of each probe
+    kernel against the chip's VALU issue peak, and from them the issue slots
+    one v_mad_u64_u32 and one v_exp_f32 take, with the XOR probe's rate as
+    that of a full-rate instruction."""
+    import ctypes
+    import torch
+    from paper_2002_12921_amd import _lib
+
+    L = _lib.lib()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    scratch = torch.empty(4 * 256 * cus * 8, dtype=torch.uint8, device="cuda")
+    ms = (ctypes.c_double * 4)()
+    blocks = ctypes.c_int32()
+    _lib.check(L.vegas_probe_issue_rates(ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), PROBE_ITERS, ms,
+                                         ctypes.byref(blocks), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "probe_issue_rates")
+    threads = blocks.value * 256
+    out = {"blocks": blocks.value, "iters": PROBE_ITERS}
+    rates = {}
+    for i, (name, per_step) in enumerate(PROBE_KERNELS):
+        rate = PROBE_ITERS * threads * per_step / (ms[i] * 1e-3)
+        rates[name] = rate
+        out[name] = {"ms": ms[i], "lane_instr_per_s": rate, "frac_of_peak": rate / PEAK_SLOTS}
+    full = rates["bitop3"]
+    steps = PROBE_ITERS * threads
+    # mad kernel: 16 full-rate instructions and 8 multiply-adds of w slots each
+    out["mad_u64_u32_slots"] = (ms[0] * 1e-3 * full / steps - 16) / 8
+    out["exp_f32_slots"] = ms[3] * 1e-3 * full / steps / 8
+    out["fma_f32_slots"] = ms[2] * 1e-3 * full / steps / 8
+    return out
 
 
 def copy_probe():
@@ -506,6 +612,8 @@ def main():
     ap.add_argument("--fp64-only", action="store_true",
                     help="only time the FP64 adaptation step (for profiling the FP64 event kernel)")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only run the VALU issue-rate probe")
     ap.add_argument("--phase-split", action="store_true",
                     help="only time iterations with/without refinement and without histograms")
     args = ap.parse_args()
@@ -518,6 +626,13 @@ def main():
               "single-device by design", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline's worker processes start before anything touches the GPU
+    pool, workers = None, 0
+    if not (args.no_cpu_baseline or args.copy_probe or args.phase_split or args.fp64_only or args.issue_probe):
+        import multiprocessing as mp
+        workers = max(1, min(len(os.sched_getaffinity(0)), CPU_WORKERS))
+        pool = mp.get_context("spawn").Pool(workers)
+
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -525,6 +640,9 @@ def main():
         copy_probe()
     if args.phase_split:
         print(json.dumps({"phase_split": phase_split(args.steps)}), flush=True)
+        return
+    if args.issue_probe:
+        print(json.dumps({"issue_probe": issue_probe()}), flush=True)
         return
     if args.fp64_only:
         r = time_path("fp64", args.steps, args.warmup)
@@ -554,7 +672,7 @@ def main():
     t_k = mixed["event_kernel_ms"] * 1e-3
     achieved = slots * EVENTS / t_k / 1e12
     peak = PEAK_SLOTS / 1e12
-    traffic, traffic_note = measured_traffic()
+    traffic, valu_busy, traffic_note = measured_counters()
     out = {
         "metric": METRIC,
         "value": mixed["events_per_s"],
@@ -574,7 +692,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_sample (event kernel)", "achieved": achieved,
                      "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_note": traffic_note,
-                     "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"]},
+                     "alg_slots_per_event": slots, "kernel_ms": mixed["event_kernel_ms"],
+                     "valu_busy_counters": valu_busy},
         "event_kernel_ms_in_step": mixed["event_kernel_ms_in_step"],
         "merge_kernel_ms_in_step": mixed["merge_kernel_ms_in_step"],
         "wall_ms_per_step": mixed["wall_ms_per_step"],
@@ -614,9 +733,16 @@ def main():
                 "event_kernel_ms": u["event_kernel_ms"], "launch": u["launch"],
                 "compile_and_init_s": u["init_s"],
                 "over_builtin": u["events_per_s"] / builtin["events_per_s"] if builtin else None}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+    if not args.mixed_only:
+        out["issue_probe"] = issue_probe()
+    if pool is not None:
+        lock = {"fp32_mixed": mixed["lockstep"]}
+        if fp64 is not None:
+            lock["fp64"] = fp64["lockstep"]
+        out["cpu_baseline"] = cpu_baseline(pool, workers, args.cpu_iters, lock)
         out["cpu_baseline"]["gpu_over_cpu"] = mixed["events_per_s"] / out["cpu_baseline"]["value"]
+        pool.close()
+        pool.join()
     print(json.dumps(out), flush=True)
 
 

@@ -202,6 +202,26 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precisi
 vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,
                            vegas_stream_t stream);
 
+/* The forward pass of a differentiable estimate, with its gradient (Gaussian
+ * integrand only; one whole iteration without histograms:
+ * flags must hold VEGAS_ITER_FULL and VEGAS_NO_HIST, and may add
+ * VEGAS_NO_COMBINE or VEGAS_NO_RECORD): as vegas_iterate -- the same events,
+ * so the same estimate bit for bit -- and the same kernel also sums, as
+ * vegas_adjoint does, each event's contribution to the gradient of the
+ * estimate with respect to theta = (mu[0..d-1], a) (the derivative of
+ * Eq. lepage's estimate with respect to its centre and width) at the
+ * current grid and parameters:
+ *   dev_G[j] = (1/M) sum_e w_e df/dtheta_j(x_e),  j = 0..d   (device FP64[d+1]).
+ * A backward pass then needs no second sweep over the events:
+ * vegas_grad_scale(dev_G, gout, grad) gives gout * dev_G. */
+vegas_status vegas_iterate_grad(vegas_ctx* ctx, int64_t n_events, uint32_t flags, double* dev_G,
+                                vegas_stream_t stream);
+
+/* dev_grad[j] = (*dev_gout) * dev_G[j], j < n (1 <= n <= 65), each rounded
+ * once to FP64 or (grad_fp32) FP32; all pointers device memory. */
+vegas_status vegas_grad_scale(const double* dev_G, const double* dev_gout, void* dev_grad, int32_t n,
+                              int32_t grad_fp32, vegas_stream_t stream);
+
 /* The refinement stage that follows a finished pass (sec. 2.2: once the
  * integration pass is done, the way points are generated is adapted): the
  * grid is refined from the histograms of the last completed iteration
@@ -317,6 +337,19 @@ vegas_status vegas_timing_read(vegas_ctx* ctx, double* sample_ms, double* merge_
 vegas_status vegas_time_event_kernel(vegas_ctx* ctx, int64_t n_events, int32_t reps, int32_t no_hist,
                                      double* ms, vegas_stream_t stream);
 
+/* Issue-rate probe of the VALU instruction classes the event kernel's
+ * throughput bound weighs (measurement only): four kernels, each thread
+ * running `iters` steps of eight independent chains of
+ *   0: v_mad_u64_u32 + v_bitop3_b32 (+ a register move), as in Philox,
+ *   1: v_bitop3_b32,  2: v_fma_f32,  3: v_exp_f32 (a transcendental),
+ * launched with 8 waves per SIMD on every compute unit (*host_blocks blocks
+ * of 256 threads), each timed with HIP events after one warm-up launch:
+ * host_ms[0..3] = milliseconds per launch.  dev_scratch receives one word
+ * per thread (4 * 256 * *host_blocks bytes at least; EWORKSPACE otherwise).
+ * Synchronises. */
+vegas_status vegas_probe_issue_rates(void* dev_scratch, size_t bytes, int32_t iters, double* host_ms,
+                                     int32_t* host_blocks, vegas_stream_t stream);
+
 /* Free the host context (the workspace stays the caller's). */
 vegas_status vegas_destroy(vegas_ctx* ctx);
 
@@ -330,7 +363,9 @@ const char* vegas_last_error(void);
  * problem; iterations 0..n_adapt-1 refine after themselves and are left out
  * of the combination, the remaining ones are combined on the frozen grid.
  * All iterations of all problems are recorded once as a HIP graph at plan
- * time and replayed by vegas_batch_run (one graph launch).
+ * time and replayed by vegas_batch_run (one graph launch).  The plan's
+ * tuning runs iterations of the batch; it leaves every problem at its start
+ * (uniform grid, nothing recorded).  Synchronises.
  * ------------------------------------------------------------------------- */
 vegas_status vegas_batch_workspace_size(const vegas_desc* descs, const int64_t* n_events,
                                         int32_t n, size_t* bytes);
@@ -339,15 +374,44 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
                               int32_t n_adapt, vegas_stream_t stream);
 /* Restart every problem from the uniform grid and t = 0, then run. */
 vegas_status vegas_batch_run(vegas_batch* batch, vegas_stream_t stream);
+/* Iteration k of every problem, eagerly, with the kernels the graph records
+ * (for checks and step-by-step use): k = 0 first restarts every problem; the
+ * steps run in order 0, 1, ..., n_iter-1 (ESTATE otherwise), and after the
+ * last one the state is that of vegas_batch_run.  Iterations k < n_adapt
+ * refine after themselves; later ones run without histograms. */
+vegas_status vegas_batch_step(vegas_batch* batch, int32_t k, vegas_stream_t stream);
+/* Sums (S1, S2) and histograms H[d_p][N_p] of problem p's last iteration
+ * (host FP64; either pointer may be NULL; H is zero after an iteration
+ * without histograms).  Synchronises. */
+vegas_status vegas_batch_get_iteration(vegas_batch* batch, int32_t p, double* host_sums, double* host_hist,
+                                       vegas_stream_t stream);
 /* Results of every problem (host array of n).  Synchronises. */
 vegas_status vegas_batch_results(vegas_batch* batch, vegas_result_t* host_out,
                                  vegas_stream_t stream);
-/* Schedule chosen at plan time: events per work item (tile), blocks of the
- * persistent event kernel, number of work items per iteration, and the timed
- * iteration of the chosen tile during tuning (ms; 0 when the tile was forced
- * with the environment variable VEGAS_BATCH_TILE).  Any pointer may be NULL. */
+/* Schedule chosen at plan time.  The plan groups problems by dimension
+ * bucket (d <= 4, 8, 16, 32, 64), one launch of the persistent event kernel
+ * per bucket, and tunes on the batch itself, timing with HIP events: first
+ * the tile (events per work item, which also sets events per thread) over
+ * 8192 ... 131072, then each bucket's launch shape, threads per block
+ * {1024, 512, 256} x histogram replicas {1, 2, 4, 8, 16} (those whose LDS
+ * fits), each bucket keeping its fastest.  A bucket's time is that of its
+ * launches in one run: n_adapt with histograms and n_iter - n_adapt without.
+ * Environment: VEGAS_BATCH_TILE, VEGAS_BATCH_THREADS, VEGAS_BATCH_REPLICAS
+ * force a value (that dimension is not tuned); VEGAS_BATCH_TUNE_CACHE names
+ * a file where unforced choices are kept per (device, batch) and read back
+ * instead of tuning again.
+ * vegas_batch_schedule: the tile, the largest bucket launch (blocks), the
+ * work items per iteration and the chosen buckets' summed time (ms; 0 when
+ * nothing was timed).  Any pointer may be NULL. */
 vegas_status vegas_batch_schedule(const vegas_batch* batch, int64_t* tile_events, int32_t* blocks,
                                   int32_t* n_items, double* tuned_ms);
+/* Bucket q of the schedule (q < 0: only *n_buckets and *from_cache): its
+ * largest dimension, threads per block, histogram replicas, blocks of its
+ * launch and timed ms per run (0 if not timed); *from_cache = 1 when the
+ * schedule came from the tuning cache.  Any pointer may be NULL. */
+vegas_status vegas_batch_bucket(const vegas_batch* batch, int32_t q, int32_t* n_buckets, int32_t* dmax,
+                                int32_t* threads, int32_t* replicas, int32_t* blocks, double* tuned_ms,
+                                int32_t* from_cache);
 /* Edges of problem p (host FP64 [d_p][N_p+1]).  Synchronises. */
 vegas_status vegas_batch_get_edges(vegas_batch* batch, int32_t p, double* host_edges,
                                    vegas_stream_t stream);

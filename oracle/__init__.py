@@ -50,10 +50,15 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle; VEGAS_ORACLE_LIB names another build of the same
+    source to load instead (the sanitizer build of paper_2002_12921_amd/sanitize.py)."""
     global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("VEGAS_ORACLE_LIB")
+        if not path:
+            build(force=False)
+            path = _LIB
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         d, u32, u64, i32 = ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
         pd, pi32, pu32, pp = P(d), P(i32), P(u32), P(_Problem)

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvegas_gfx950.so")
+# VEGAS_LIB names another build of the same sources to load instead (the
+# host-sanitizer build of sanitize.py)
+LIB_PATH = os.environ.get("VEGAS_LIB") or os.path.join(HERE, "libvegas_gfx950.so")
 
 VEGAS_OK, VEGAS_EINVAL, VEGAS_ESTATE, VEGAS_EWORKSPACE = 0, -1, -2, -3
 VEGAS_EHIP, VEGAS_ENONFINITE, VEGAS_EUNSUPPORTED, VEGAS_ECOMPILE = -4, -5, -6, -7
@@ -23,16 +25,18 @@ CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST, NO_RECORD = 1, 2
 
 # every symbol include/vegas.h declares
 EXPORTS = [
-    "vegas_workspace_size", "vegas_init_grid", "vegas_init_grid_noalloc", "vegas_init_user", "vegas_user_compile", "vegas_iterate", "vegas_refine", "vegas_result",
+    "vegas_workspace_size", "vegas_init_grid", "vegas_init_grid_noalloc", "vegas_init_user", "vegas_user_compile", "vegas_iterate",
+    "vegas_iterate_grad", "vegas_grad_scale", "vegas_refine", "vegas_result",
     "vegas_reset_results", "vegas_set_params_device", "vegas_get_params_device", "vegas_get_versions",
     "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
     "vegas_get_iteration", "vegas_state_size", "vegas_get_state", "vegas_set_state",
     "vegas_get_iteration_index", "vegas_set_launch", "vegas_set_hist_replicas", "vegas_get_launch",
-    "vegas_timing_enable", "vegas_timing_read", "vegas_time_event_kernel",
+    "vegas_timing_enable", "vegas_timing_read", "vegas_time_event_kernel", "vegas_probe_issue_rates",
     "vegas_destroy", "vegas_last_error",
-    "vegas_batch_workspace_size", "vegas_batch_plan", "vegas_batch_run", "vegas_batch_results",
-    "vegas_batch_get_edges", "vegas_batch_schedule", "vegas_batch_destroy",
+    "vegas_batch_workspace_size", "vegas_batch_plan", "vegas_batch_run", "vegas_batch_step",
+    "vegas_batch_get_iteration", "vegas_batch_results",
+    "vegas_batch_get_edges", "vegas_batch_schedule", "vegas_batch_bucket", "vegas_batch_destroy",
 ]
 
 
@@ -83,6 +87,8 @@ def lib() -> ctypes.CDLL:
         "vegas_init_user": [P(vp), P(Desc), ctypes.c_char_p, vp, sz, vp],
         "vegas_user_compile": [ctypes.c_char_p, i32, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],
+        "vegas_iterate_grad": [vp, i64, u32, vp, vp],
+        "vegas_grad_scale": [vp, vp, vp, i32, i32, vp],
         "vegas_refine": [vp, vp],
         "vegas_result": [vp, P(Result), vp],
         "vegas_reset_results": [vp, vp],
@@ -105,13 +111,17 @@ def lib() -> ctypes.CDLL:
         "vegas_timing_enable": [vp, i32],
         "vegas_timing_read": [vp, pd, pd, P(i64)],
         "vegas_time_event_kernel": [vp, i64, i32, i32, pd, vp],
+        "vegas_probe_issue_rates": [vp, sz, i32, pd, P(i32), vp],
         "vegas_destroy": [vp],
         "vegas_batch_workspace_size": [P(Desc), P(i64), i32, P(sz)],
         "vegas_batch_plan": [P(vp), P(Desc), P(i64), i32, vp, sz, i32, i32, vp],
         "vegas_batch_run": [vp, vp],
+        "vegas_batch_step": [vp, i32, vp],
+        "vegas_batch_get_iteration": [vp, i32, pd, pd, vp],
         "vegas_batch_results": [vp, P(Result), vp],
         "vegas_batch_get_edges": [vp, i32, pd, vp],
         "vegas_batch_schedule": [vp, P(i64), P(i32), P(i32), pd],
+        "vegas_batch_bucket": [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32), pd, P(i32)],
         "vegas_batch_destroy": [vp],
     }
     for name, args in sig.items():

@@ -1,17 +1,20 @@
 """Differentiable Vegas estimate of a Gaussian integral.
 
-VegasIntegral.apply(mu, a, vegas, n_events) returns the estimate of
+VegasIntegral.apply(mu, a, vegas, n_events, fused) returns the estimate of
 integral_[0,1]^d (a sqrt(pi))^-d exp(-sum_i (x_i - mu_i)^2 / a^2) dx from one
 iteration of n_events events on the context's current grid (the grid is
 frozen: nothing is refined, and the iteration is not recorded, so any number
-of forward passes fit one context).  Its backward pass regenerates the same
-points (counter-based Philox, same iteration index) and runs the library's
-adjoint kernel, which returns (1/M) sum_e w_e df/dtheta(x_e) for
-theta = (mu, a), times the incoming gradient.  Nothing per event is stored
-between the passes.
+of forward passes fit one context).  Its gradient with respect to (mu, a) is
+(1/M) sum_e w_e df/dtheta(x_e) over the same events, at fixed samples and
+grid, times the incoming gradient.
 
-The backward pass needs the grid and parameters its forward pass used.  If
-the context's parameters changed in between (another forward pass on the same
+fused=True (the default): the forward launch itself also sums the gradient
+terms (vegas_iterate_grad: the same events and the same estimate, bit for
+bit), so backward only scales d + 1 numbers.  fused=False: the backward pass
+regenerates the same points (counter-based Philox, same iteration index) in
+the library's adjoint kernel (vegas_adjoint); nothing per event is stored
+between the passes, but it needs the forward's grid and parameters: if the
+context's parameters changed in between (another forward pass on the same
 context, say), they are set back for the adjoint and restored afterwards; if
 its grid changed (a refinement, new edges or a loaded state), backward raises.
 """
@@ -24,7 +27,7 @@ from .integrator import Vegas
 
 class VegasIntegral(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mu: torch.Tensor, a: torch.Tensor, vegas: Vegas, n_events: int):
+    def forward(ctx, mu: torch.Tensor, a: torch.Tensor, vegas: Vegas, n_events: int, fused: bool = True):
         if vegas.desc.integrand != 0:
             raise ValueError("VegasIntegral needs a Gaussian-integrand context")
         d = vegas.dim
@@ -36,14 +39,22 @@ class VegasIntegral(torch.autograd.Function):
         params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
         vegas.set_params_device(params)
         t = vegas.iteration_index
-        # frozen grid: no histograms (the sums are bitwise those of the
-        # histogram variant) and no record slot
-        vegas.iterate(n_events, refine=False, combine=False, hist=False, record=False)
         out = torch.empty(2, dtype=torch.float64, device=mu.device)
+        ctx.G = None
+        if fused:
+            # frozen grid: no histograms, no record slot; the gradient terms
+            # are summed in the same launch
+            G = torch.empty(d + 1, dtype=torch.float64, device=mu.device)
+            vegas.iterate_grad(n_events, G, combine=False, record=False)
+            ctx.G = G
+        else:
+            # frozen grid: no histograms (the sums are bitwise those of the
+            # histogram variant) and no record slot
+            vegas.iterate(n_events, refine=False, combine=False, hist=False, record=False)
+            ctx.params = params  # a tensor of its own: nothing else writes it
+            ctx.versions = vegas.versions()
         vegas.last_iteration_device(out)
         ctx.vegas, ctx.t, ctx.n = vegas, t, n_events
-        ctx.params = params  # a tensor of its own: nothing else writes it
-        ctx.versions = vegas.versions()
         ctx.mu_meta = (mu.dtype, mu.shape)
         ctx.a_meta = (a.dtype, a.shape)
         return out[0]
@@ -52,30 +63,30 @@ class VegasIntegral(torch.autograd.Function):
     def backward(ctx, gout: torch.Tensor):
         v: Vegas = ctx.vegas
         d = v.dim
-        grid_v, params_v = v.versions()
-        if grid_v != ctx.versions[0]:
-            raise RuntimeError("VegasIntegral.backward: the context's grid changed after the forward pass "
-                               "(refinement, set_edges or set_state); the adjoint needs the forward grid")
-        restore = None
-        if params_v != ctx.versions[1]:
-            restore = v.get_params_device()
-            v.set_params_device(ctx.params)
         g = gout.detach().to(torch.float64).reshape(1).contiguous()
         mu_dtype, mu_shape = ctx.mu_meta
         a_dtype, a_shape = ctx.a_meta
-        if mu_dtype == a_dtype and mu_dtype in (torch.float32, torch.float64):
-            # the adjoint writes the parameters' dtype itself
-            grad = torch.empty(d + 1, dtype=mu_dtype, device=g.device)
-            v.adjoint(ctx.t, ctx.n, g, grad)
-            gmu, ga = grad[:d].reshape(mu_shape), grad[d].reshape(a_shape)
+        same = mu_dtype == a_dtype and mu_dtype in (torch.float32, torch.float64)
+        # the library writes the parameters' dtype itself (one rounding)
+        grad = torch.empty(d + 1, dtype=mu_dtype if same else torch.float64, device=g.device)
+        if ctx.G is not None:
+            v.grad_scale(ctx.G, g, grad)
         else:
-            grad = torch.empty(d + 1, dtype=torch.float64, device=g.device)
+            grid_v, params_v = v.versions()
+            if grid_v != ctx.versions[0]:
+                raise RuntimeError("VegasIntegral.backward: the context's grid changed after the forward pass "
+                                   "(refinement, set_edges or set_state); the adjoint needs the forward grid")
+            restore = None
+            if params_v != ctx.versions[1]:
+                restore = v.get_params_device()
+                v.set_params_device(ctx.params)
             v.adjoint(ctx.t, ctx.n, g, grad)
-            gmu, ga = grad[:d].to(mu_dtype).reshape(mu_shape), grad[d].to(a_dtype).reshape(a_shape)
-        if restore is not None:
-            v.set_params_device(restore)
-        return gmu, ga, None, None
+            if restore is not None:
+                v.set_params_device(restore)
+        if same:
+            return grad[:d].reshape(mu_shape), grad[d].reshape(a_shape), None, None, None
+        return grad[:d].to(mu_dtype).reshape(mu_shape), grad[d].to(a_dtype).reshape(a_shape), None, None, None
 
 
-def vegas_integral(mu: torch.Tensor, a: torch.Tensor, vegas: Vegas, n_events: int) -> torch.Tensor:
-    return VegasIntegral.apply(mu, a, vegas, n_events)
+def vegas_integral(mu: torch.Tensor, a: torch.Tensor, vegas: Vegas, n_events: int, fused: bool = True) -> torch.Tensor:
+    return VegasIntegral.apply(mu, a, vegas, n_events, fused)

@@ -59,6 +59,19 @@ class VegasBatch:
     def run(self):
         check(lib().vegas_batch_run(self._b, self._s()), "batch_run")
 
+    def step(self, k: int):
+        """Iteration k of every problem, eagerly (k = 0 restarts; in order)."""
+        check(lib().vegas_batch_step(self._b, int(k), self._s()), "batch_step")
+
+    def last_iteration(self, p: int):
+        """(S1, S2, H[d_p, N_p]) of problem p's last iteration."""
+        sums = np.zeros(2)
+        H = np.zeros((self.dims[p], self.bins[p]))
+        P = ctypes.POINTER(ctypes.c_double)
+        check(lib().vegas_batch_get_iteration(self._b, p, sums.ctypes.data_as(P), H.ctypes.data_as(P),
+                                              self._s()), "batch_get_iteration")
+        return sums[0], sums[1], H
+
     def results(self, allow_nonfinite: bool = False) -> list:
         out = (_lib.Result * self.n)()
         st = lib().vegas_batch_results(self._b, out, self._s())
@@ -76,7 +89,22 @@ class VegasBatch:
         t, b, n, ms = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         check(lib().vegas_batch_schedule(self._b, ctypes.byref(t), ctypes.byref(b), ctypes.byref(n),
                                          ctypes.byref(ms)), "batch_schedule")
-        return {"tile_events": t.value, "blocks": b.value, "n_items": n.value, "tuned_ms": ms.value}
+        out = {"tile_events": t.value, "blocks": b.value, "n_items": n.value, "tuned_ms": ms.value}
+        L = lib()
+        nb, fc = ctypes.c_int32(), ctypes.c_int32()
+        check(L.vegas_batch_bucket(self._b, -1, ctypes.byref(nb), None, None, None, None, None, ctypes.byref(fc)),
+              "batch_bucket")
+        buckets = []
+        for q in range(nb.value):
+            dm, th, rp, bl, tm = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                                  ctypes.c_double())
+            check(L.vegas_batch_bucket(self._b, q, None, ctypes.byref(dm), ctypes.byref(th), ctypes.byref(rp),
+                                       ctypes.byref(bl), ctypes.byref(tm), None), "batch_bucket")
+            buckets.append({"dmax": dm.value, "threads": th.value, "replicas": rp.value, "blocks": bl.value,
+                            "tuned_ms": tm.value})
+        out["buckets"] = buckets
+        out["from_cache"] = bool(fc.value)
+        return out
 
     def close(self):
         if getattr(self, "_b", None):

@@ -8,7 +8,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "capi_util.hpp"
@@ -112,8 +115,10 @@ struct vegas_batch {
         int blocks = 0;
         int threads = kBlock;
         int hrep_log2 = 0;
+        double tuned_ms = 0.0;  // its launches' time in one run (n_adapt with, the rest without histograms)
     };
     std::vector<Bucket> buckets;
+    bool tuned_from_cache = false;
     int blocks = 0;  // the largest bucket launch (reported by vegas_batch_schedule)
     uint64_t tile = 0;
     int n_items = 0;
@@ -123,6 +128,8 @@ struct vegas_batch {
     hipGraphExec_t exec = nullptr;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
+    int next_step = 0;  // the iteration vegas_batch_step runs next (0 after a graph run)
+    size_t max_pstride = 0;
 
     char* at(size_t off) const { return static_cast<char*>(ws) + off; }
     BatchArgs args() const
@@ -199,7 +206,8 @@ vegas_status upload_schedule(vegas_batch* b, uint64_t T)
 
 // One iteration of every problem: persistent event kernel, then the per-problem
 // reduction (records iteration k; refines while k < n_adapt).
-vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s)
+// ev (tuning only): HIP events recorded before and after each bucket's launch.
+vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s, const hipEvent_t* ev = nullptr)
 {
     BatchArgs a = b->args();
     a.t = uint32_t(k);
@@ -212,11 +220,163 @@ vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s)
         ab.item_lo = bk.lo;
         ab.item_hi = bk.hi;
         ab.hrep_log2 = bk.hrep_log2;
+        if (ev) VEGAS_HIP(hipEventRecord(ev[2 * q], s));
         VEGAS_HIP(launch_batch_sample(b->prec, b->kind, bk.dmax, bk.lds, ab, bk.blocks, bk.threads, adapt, s));
+        if (ev) VEGAS_HIP(hipEventRecord(ev[2 * q + 1], s));
     }
     const int flags = adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : MERGE_NO_HIST;
     VEGAS_HIP(launch_batch_finish(a, b->dmax, b->kind, k, flags, s));
     return VEGAS_OK;
+}
+
+// A launch shape of a bucket's event kernel.
+struct Shape {
+    int threads, l2;  // threads per block, log2 of the histogram replicas
+    size_t lds;       // dynamic LDS per block
+    int blocks, bpc;  // blocks of the launch (resident ones on every CU), blocks per CU
+};
+
+void apply_shape(vegas_batch::Bucket& bk, const Shape& sh)
+{
+    bk.threads = sh.threads;
+    bk.hrep_log2 = sh.l2;
+    bk.lds = sh.lds;
+    bk.blocks = sh.blocks;
+}
+
+int env_int(const char* name)
+{
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : 0;
+}
+
+struct Timer {
+    std::vector<hipEvent_t> ev;
+    hipError_t init(int n)
+    {
+        ev.assign(size_t(n), nullptr);
+        for (auto& e : ev) {
+            const hipError_t he = hipEventCreate(&e);
+            if (he != hipSuccess) {
+                e = nullptr;
+                return he;
+            }
+        }
+        return hipSuccess;
+    }
+    ~Timer()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Time of each bucket's launches in one run under the current schedule:
+// n_adapt times its launch with histograms plus (n_iter - n_adapt) times its
+// launch without, each the fastest of two launches after a warm-up
+// iteration.  The iterations timed here leave the problems' state
+// (grids, records) arbitrary: the recorded run restarts every problem.
+vegas_status time_schedule(vegas_batch* b, Timer& tm, std::vector<double>& per)
+{
+    hipStream_t s = b->priv;
+    const size_t nb = b->buckets.size();
+    per.assign(nb, 0.0);
+    VEGAS_HIP(launch_batch_reset(b->args(), b->dmax, kBatchMaxIter, b->kind, s));
+    vegas_status st = enqueue_iteration(b, 0, s);
+    if (st != VEGAS_OK) return st;
+    const int kinds[2] = {b->n_adapt > 0 ? 0 : -1, b->n_adapt < b->n_iter ? b->n_adapt : -1};
+    const double weight[2] = {double(b->n_adapt), double(b->n_iter - b->n_adapt)};
+    for (int w = 0; w < 2; ++w) {
+        if (kinds[w] < 0) continue;
+        std::vector<double> best(nb, 1e300);
+        for (int r = 0; r < 2; ++r) {
+            if ((st = enqueue_iteration(b, kinds[w], s, tm.ev.data())) != VEGAS_OK) return st;
+            VEGAS_HIP(hipEventSynchronize(tm.ev[2 * nb - 1]));
+            for (size_t q = 0; q < nb; ++q) {
+                float ms = 0.f;
+                VEGAS_HIP(hipEventElapsedTime(&ms, tm.ev[2 * q], tm.ev[2 * q + 1]));
+                best[q] = std::min(best[q], double(ms));
+            }
+        }
+        for (size_t q = 0; q < nb; ++q) per[q] += weight[w] * best[q];
+    }
+    VEGAS_HIP(hipStreamSynchronize(s));
+    return VEGAS_OK;
+}
+
+// Tuning-cache key: the device (architecture, compute units) and the batch
+// (precision, integrand, sizes of every problem, iteration counts).
+std::string tune_key(const vegas_batch* b, int dev, int cus)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over (d, N, M) of every problem
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int p = 0; p < b->n; ++p) {
+        mix(uint64_t(b->dims[p]));
+        mix(uint64_t(b->bins[p]));
+        mix(uint64_t(b->events[p]));
+    }
+    std::ostringstream o;
+    o << "vegas-batch-v1 " << arch << " cu" << cus << " p" << b->prec << " k" << b->kind << " n" << b->n << " i"
+      << b->n_iter << " a" << b->n_adapt << " h" << std::hex << h;
+    return o.str();
+}
+
+// A cache line: key, then "| tile n_buckets (dmax threads l2 ms)...".
+bool read_tuned(const char* path, const std::string& key, vegas_batch* b,
+                const std::vector<std::vector<Shape>>& shapes, uint64_t& tile)
+{
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find(" | ");
+        if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
+        std::istringstream in(line.substr(bar + 3));
+        uint64_t T = 0;
+        size_t nb = 0;
+        if (!(in >> T >> nb) || nb != b->buckets.size()) continue;
+        if (std::find(std::begin(kTileCandidates), std::end(kTileCandidates), T) == std::end(kTileCandidates)) continue;
+        std::vector<vegas_batch::Bucket> got = b->buckets;
+        bool ok = true;
+        for (size_t q = 0; q < nb && ok; ++q) {
+            int dm = 0, th = 0, l2 = 0;
+            double ms = 0.0;
+            ok = bool(in >> dm >> th >> l2 >> ms) && dm == got[q].dmax;
+            const Shape* hit = nullptr;
+            for (const Shape& sh : shapes[q])
+                if (sh.threads == th && sh.l2 == l2) hit = &sh;
+            if (!ok || !hit) {
+                ok = false;
+                break;
+            }
+            apply_shape(got[q], *hit);
+            got[q].tuned_ms = ms;
+        }
+        if (!ok) continue;
+        b->buckets = got;
+        tile = T;
+        return true;
+    }
+    return false;
+}
+
+void write_tuned(const char* path, const std::string& key, const vegas_batch* b, uint64_t tile)
+{
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;  // the cache is an optimisation: a read-only place only costs the tuning
+    f.precision(17);  // doubles read back exactly
+    f << key << " | " << tile << " " << b->buckets.size();
+    for (const auto& bk : b->buckets) f << " " << bk.dmax << " " << bk.threads << " " << bk.hrep_log2 << " " << bk.tuned_ms;
+    f << "\n";
 }
 
 void destroy_graph(vegas_batch* b)
@@ -285,9 +445,17 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         (he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
         (he = hipStreamCreate(&b->priv)) != hipSuccess)
         return bail(fail(VEGAS_EHIP, "batch setup: %s", hipGetErrorString(he)));
-    // one event-kernel launch per dimension bucket present, each with the
-    // most histogram replicas (16, 8, 4, 2) that keep the resident blocks per
-    // CU of a single copy for that bucket's largest table and histogram
+    // one event-kernel launch per dimension bucket present; its launch shapes
+    // (threads x histogram replicas that fit the LDS of the bucket's largest
+    // table and histogram), optionally restricted by VEGAS_BATCH_THREADS /
+    // VEGAS_BATCH_REPLICAS
+    const int force_threads = env_int("VEGAS_BATCH_THREADS");
+    const int force_reps = env_int("VEGAS_BATCH_REPLICAS");
+    if (force_threads && force_threads != 256 && force_threads != 512 && force_threads != 1024)
+        return bail(fail(VEGAS_EINVAL, "VEGAS_BATCH_THREADS must be 256, 512 or 1024"));
+    if (force_reps && (force_reps < 1 || force_reps > 16 || (force_reps & (force_reps - 1))))
+        return bail(fail(VEGAS_EINVAL, "VEGAS_BATCH_REPLICAS must be 1, 2, 4, 8 or 16"));
+    std::vector<std::vector<Shape>> shapes;
     for (int dm : {64, 32, 16, 8, 4}) {
         auto lds_for = [&](int rep) {
             size_t m = 0;
@@ -297,35 +465,43 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
             return m;
         };
         if (lds_for(1) == 0) continue;  // no problem in this bucket
-        vegas_batch::Bucket bk;
-        bk.dmax = dm;
-        // block size and replicas scored as for a single problem: resident
-        // waves x a replica factor (ties keep the larger block)
-        static const double kRepFactor[5] = {0.5, 0.65, 0.8, 0.93, 1.0};
-        double best = -1.0;
-        for (int th : {1024, 512}) {
+        std::vector<Shape> cand;
+        for (int th : {1024, 512, 256}) {
+            if (force_threads && th != force_threads) continue;
             for (int l2 = 4; l2 >= 0; --l2) {
+                if (force_reps && (1 << l2) != force_reps) continue;
                 const size_t lds = lds_for(1 << l2);
                 // 256: the kernel's static LDS (work item, wave partials), and
                 // the discontinuous integrand's thresholds
                 if (lds + 256 + (b->kind == VEGAS_GENZ_DISC ? sizeof(uint64_t) * dm : 0) > kLdsLimit) continue;
                 const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th);
-                const double score = double(bpc * th / 64) * kRepFactor[l2];
-                if (score > best + 1e-9) {
-                    best = score;
-                    bk.threads = th;
-                    bk.hrep_log2 = l2;
-                    bk.lds = lds;
-                    bk.blocks = std::max(1, cus * bpc);
-                }
+                cand.push_back(Shape{th, l2, lds, std::max(1, cus * bpc), bpc});
             }
         }
-        if (best < 0.0)
-            return bail(fail(VEGAS_EUNSUPPORTED, "no launch shape of the batch event kernel fits the d <= %d problems", dm));
-        b->blocks = std::max(b->blocks, bk.blocks);
+        if (cand.empty())
+            return bail(fail(VEGAS_EUNSUPPORTED, "no launch shape of the batch event kernel fits the d <= %d problems%s",
+                             dm, (force_threads || force_reps) ? " (with the forced threads / replicas)" : ""));
+        // starting point: the single-problem score (resident waves x a
+        // replica factor, ties to the larger block)
+        static const double kRepFactor[5] = {0.5, 0.65, 0.8, 0.93, 1.0};
+        size_t first = 0;
+        double best = -1.0;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            const double score = double(cand[c].bpc * cand[c].threads / 64) * kRepFactor[cand[c].l2] *
+                                 (cand[c].threads == 256 ? 0.92 : 1.0);
+            if (score > best + 1e-9) {
+                best = score;
+                first = c;
+            }
+        }
+        vegas_batch::Bucket bk;
+        bk.dmax = dm;
+        apply_shape(bk, cand[first]);
         b->buckets.push_back(bk);
+        shapes.push_back(cand);
     }
-    b->pinned_bytes = sizeof(DevResult) * n + 4096;
+    for (int p = 0; p < n; ++p) b->max_pstride = std::max(b->max_pstride, size_t(2 + descs[p].dim * descs[p].n_bins));
+    b->pinned_bytes = std::max(sizeof(DevResult) * n, sizeof(double) * b->max_pstride) + 4096;
     if ((he = hipHostMalloc(&b->pinned, b->pinned_bytes, hipHostMallocDefault)) != hipSuccess) {
         b->pinned = nullptr;
         return bail(fail(VEGAS_EHIP, "hipHostMalloc: %s", hipGetErrorString(he)));
@@ -361,39 +537,71 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
             return bail(fail(VEGAS_EHIP, "batch prepare: %s", hipGetErrorString(he)));
     }
 
-    // autotune the tile size: one warm and one timed iteration per candidate
+    // the schedule: tile size (events per work item), then each bucket's
+    // launch shape, timed on this batch (or read from the tuning cache)
     const char* forced = std::getenv("VEGAS_BATCH_TILE");
-    uint64_t best = forced ? uint64_t(std::strtoull(forced, nullptr, 10)) : 0;
-    if (best && std::find(std::begin(kTileCandidates), std::end(kTileCandidates), best) == std::end(kTileCandidates))
+    uint64_t tile = forced ? uint64_t(std::strtoull(forced, nullptr, 10)) : 0;
+    if (tile && std::find(std::begin(kTileCandidates), std::end(kTileCandidates), tile) == std::end(kTileCandidates))
         return bail(fail(VEGAS_EINVAL, "VEGAS_BATCH_TILE must be one of 8192 ... 131072"));
-    if (!best) {
-        hipEvent_t e0, e1;
-        if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess)
+    const bool any_forced = tile || force_threads || force_reps;
+    const char* cache_path = std::getenv("VEGAS_BATCH_TUNE_CACHE");
+    std::string key;
+    if (cache_path && !any_forced) {
+        key = tune_key(b, dev, cus);
+        if (read_tuned(cache_path, key, b, shapes, tile)) b->tuned_from_cache = true;
+    }
+    if (!b->tuned_from_cache) {
+        Timer tm;
+        if ((he = tm.init(2 * int(b->buckets.size()))) != hipSuccess)
             return bail(fail(VEGAS_EHIP, "hipEventCreate: %s", hipGetErrorString(he)));
-        double best_ms = 1e300;
-        for (uint64_t T : kTileCandidates) {
-            if ((st = upload_schedule(b, T)) != VEGAS_OK) return bail(st);
-            BatchArgs a = b->args();
-            if ((he = launch_batch_reset(a, b->dmax, kBatchMaxIter, b->kind, b->priv)) != hipSuccess)
-                return bail(fail(VEGAS_EHIP, "reset: %s", hipGetErrorString(he)));
-            if ((st = enqueue_iteration(b, 0, b->priv)) != VEGAS_OK) return bail(st);
-            (void)hipEventRecord(e0, b->priv);
-            if ((st = enqueue_iteration(b, 1 < n_iter ? 1 : 0, b->priv)) != VEGAS_OK) return bail(st);
-            (void)hipEventRecord(e1, b->priv);
-            if ((he = hipEventSynchronize(e1)) != hipSuccess)
-                return bail(fail(VEGAS_EHIP, "tuning: %s", hipGetErrorString(he)));
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = T;
+        std::vector<double> per;
+        if (!tile) {
+            double best_ms = 1e300;
+            for (uint64_t T : kTileCandidates) {
+                if ((st = upload_schedule(b, T)) != VEGAS_OK) return bail(st);
+                if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+                double tot = 0.0;
+                for (double x : per) tot += x;
+                if (tot < best_ms) {
+                    best_ms = tot;
+                    tile = T;
+                }
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        b->tuned_ms = best_ms;
+        if ((st = upload_schedule(b, tile)) != VEGAS_OK) return bail(st);
+        if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+        for (size_t q = 0; q < b->buckets.size(); ++q) b->buckets[q].tuned_ms = per[q];
+        // each bucket's launch is timed on its own, so the buckets are tuned
+        // one after another, each keeping its fastest shape
+        for (size_t q = 0; q < b->buckets.size(); ++q) {
+            auto& bk = b->buckets[q];
+            const vegas_batch::Bucket start = bk;
+            vegas_batch::Bucket best_bk = bk;
+            for (const Shape& sh : shapes[q]) {
+                if (sh.threads == start.threads && sh.l2 == start.hrep_log2) continue;
+                apply_shape(bk, sh);
+                if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+                if (per[q] < best_bk.tuned_ms) {
+                    best_bk = bk;
+                    best_bk.tuned_ms = per[q];
+                }
+            }
+            bk = best_bk;
+        }
+        if (cache_path && !any_forced) write_tuned(cache_path, key, b, tile);
+        // the timed iterations refined grids and recorded iterations: every
+        // problem restarts, so the plan leaves the batch at its beginning
+        if ((he = launch_batch_reset(b->args(), b->dmax, kBatchMaxIter, b->kind, b->priv)) != hipSuccess ||
+            (he = hipStreamSynchronize(b->priv)) != hipSuccess)
+            return bail(fail(VEGAS_EHIP, "reset after tuning: %s", hipGetErrorString(he)));
     }
-    if ((st = upload_schedule(b, best)) != VEGAS_OK) return bail(st);
+    if ((st = upload_schedule(b, tile)) != VEGAS_OK) return bail(st);
+    b->tuned_ms = 0.0;
+    b->blocks = 0;
+    for (const auto& bk : b->buckets) {
+        b->blocks = std::max(b->blocks, bk.blocks);
+        b->tuned_ms += bk.tuned_ms;
+    }
 
     // record the whole run: restart, then n_iter iterations
     if ((he = hipStreamBeginCapture(b->priv, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -416,6 +624,36 @@ vegas_status vegas_batch_run(vegas_batch* b, vegas_stream_t stream)
 {
     if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
     VEGAS_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    b->next_step = 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_step(vegas_batch* b, int32_t k, vegas_stream_t stream)
+{
+    if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    if (k < 0 || k >= b->n_iter) return fail(VEGAS_EINVAL, "iteration %d out of [0, %d)", k, b->n_iter);
+    if (k != 0 && k != b->next_step)
+        return fail(VEGAS_ESTATE, "iteration %d next: steps run in order from 0 (asked for %d)", b->next_step, k);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (k == 0) VEGAS_HIP(launch_batch_reset(b->args(), b->dmax, b->n_iter, b->kind, s));
+    vegas_status st = enqueue_iteration(b, k, s);
+    if (st != VEGAS_OK) return st;
+    b->next_step = k + 1 < b->n_iter ? k + 1 : 0;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_get_iteration(vegas_batch* b, int32_t p, double* host_sums, double* host_hist,
+                                       vegas_stream_t stream)
+{
+    if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    if (p < 0 || p >= b->n) return fail(VEGAS_EINVAL, "problem %d out of range", p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t ps = size_t(2 + b->dims[p] * b->bins[p]);
+    VEGAS_HIP(hipMemcpyAsync(b->pinned, b->at(b->L.last[p]), sizeof(double) * ps, hipMemcpyDeviceToHost, s));
+    VEGAS_HIP(hipStreamSynchronize(s));
+    const double* v = static_cast<const double*>(b->pinned);
+    if (host_sums) std::memcpy(host_sums, v, 2 * sizeof(double));
+    if (host_hist) std::memcpy(host_hist, v + 2, sizeof(double) * (ps - 2));
     return VEGAS_OK;
 }
 
@@ -463,6 +701,23 @@ vegas_status vegas_batch_schedule(const vegas_batch* b, int64_t* tile_events, in
     if (blocks) *blocks = b->blocks;
     if (n_items) *n_items = b->n_items;
     if (tuned_ms) *tuned_ms = b->tuned_ms;
+    return VEGAS_OK;
+}
+
+vegas_status vegas_batch_bucket(const vegas_batch* b, int32_t q, int32_t* n_buckets, int32_t* dmax, int32_t* threads,
+                                int32_t* replicas, int32_t* blocks, double* tuned_ms, int32_t* from_cache)
+{
+    if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    if (n_buckets) *n_buckets = int32_t(b->buckets.size());
+    if (from_cache) *from_cache = b->tuned_from_cache ? 1 : 0;
+    if (q < 0) return VEGAS_OK;
+    if (q >= int32_t(b->buckets.size())) return fail(VEGAS_EINVAL, "bucket %d out of range", q);
+    const auto& bk = b->buckets[size_t(q)];
+    if (dmax) *dmax = bk.dmax;
+    if (threads) *threads = bk.threads;
+    if (replicas) *replicas = 1 << bk.hrep_log2;
+    if (blocks) *blocks = bk.blocks;
+    if (tuned_ms) *tuned_ms = bk.tuned_ms;
     return VEGAS_OK;
 }
 

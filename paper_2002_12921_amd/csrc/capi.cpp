@@ -472,7 +472,13 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precisi
     return st;
 }
 
-vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
+}  // extern "C"
+
+namespace {
+
+// vegas_iterate, and with dev_G (vegas_iterate_grad) the forward pass that
+// also forms the estimate's gradient into dev_G.
+vegas_status iterate_impl(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, vegas_stream_t stream)
 {
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40] (got %lld)", (long long)n);
@@ -497,17 +503,30 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
         return fail(VEGAS_ESTATE, "%d iterations recorded: call vegas_reset_results", kMaxRecords);
     if (c->t >= (int64_t(1) << 32)) return fail(VEGAS_ESTATE, "iteration index exhausted");
 
+    if (dev_G) {
+        if (c->kind != VEGAS_GAUSS) return fail(VEGAS_EUNSUPPORTED, "the gradient is implemented for the Gaussian integrand");
+        if (!begin || !end || !no_hist)
+            return fail(VEGAS_EINVAL, "the forward pass with the gradient is one whole iteration without histograms "
+                                      "(VEGAS_ITER_FULL | VEGAS_NO_HIST)");
+    }
+
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int blocks = sample_blocks(c, n);
     const SampleArgs a = sample_args(c, e0, n, no_hist);
     const bool timed = c->timing && c->n_timed < kTimedCalls;
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed], s));
-    VEGAS_HIP(launch_event_kernel(c, a, blocks, s));
+    if (dev_G)
+        VEGAS_HIP(launch_sample_grad(c->prec, a, c->P.adj_part, blocks, c->threads, s));
+    else
+        VEGAS_HIP(launch_event_kernel(c, a, blocks, s));
     if (timed) VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 1], s));
     int mf = (begin ? MERGE_BEGIN : 0) | (end ? MERGE_END : 0) | ((flags & VEGAS_NO_COMBINE) ? MERGE_NO_COMBINE : 0) |
              ((flags & VEGAS_REFINE) ? MERGE_REFINE : 0) | (no_hist ? MERGE_NO_HIST : 0) |
-             (no_record ? MERGE_NO_RECORD : 0);
-    VEGAS_HIP(launch_merge(merge_args(c, blocks, mf, double(M)), s));
+             (no_record ? MERGE_NO_RECORD : 0) | (dev_G ? MERGE_GRAD : 0);
+    MergeArgs ma = merge_args(c, blocks, mf, double(M));
+    ma.gpart = c->P.adj_part;
+    ma.grad_out = dev_G;
+    VEGAS_HIP(launch_merge(ma, s));
     if (timed) {
         VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 2], s));
         c->n_timed += 1;
@@ -524,6 +543,30 @@ vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream
         if (flags & VEGAS_REFINE) c->grid_version += 1;
         c->chunk_events = 0;
     }
+    return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
+{
+    return iterate_impl(c, n, flags, nullptr, stream);
+}
+
+vegas_status vegas_iterate_grad(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, vegas_stream_t stream)
+{
+    if (!dev_G) return fail(VEGAS_EINVAL, "dev_G is NULL");
+    return iterate_impl(c, n, flags, dev_G, stream);
+}
+
+vegas_status vegas_grad_scale(const double* dev_G, const double* dev_gout, void* dev_grad, int32_t n,
+                              int32_t grad_fp32, vegas_stream_t stream)
+{
+    if (!dev_G || !dev_gout || !dev_grad) return fail(VEGAS_EINVAL, "NULL argument");
+    if (n < 1 || n > kMaxDim + 1) return fail(VEGAS_EINVAL, "n must be in [1, %d]", kMaxDim + 1);
+    VEGAS_HIP(launch_grad_scale(dev_G, dev_gout, dev_grad, n, grad_fp32 ? 1 : 0, static_cast<hipStream_t>(stream)));
     return VEGAS_OK;
 }
 

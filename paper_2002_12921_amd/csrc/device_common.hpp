@@ -395,6 +395,35 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return t;
 }
 
+// Fixed-order sum of the (d + 1)-column rows part[rows][d + 1] of an
+// adjoint: one wave per column j (and j + 16, ...), lane l adding rows l,
+// l + 64, ... in order with two-sums, then an exact two-sum butterfly across
+// the wave (the same pair on every lane); column j times `scale` goes to
+// out[j], in FP64 or rounded once to FP32 (out_fp32).  Called by a whole
+// block of kMergeThreads threads.
+__device__ __forceinline__ void adjoint_merge_block(const double* part, int rows, int d, double scale, void* out,
+                                                    int out_fp32)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j <= d; j += kMergeThreads / 64) {
+        double s = 0.0, c = 0.0;
+        for (int r = lane; r < rows; r += 64) twosum_add(s, c, part[size_t(r) * (d + 1) + j]);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
+            twosum_add(s, c, s2);
+            c += c2;
+        }
+        if (lane == 0) {
+            const double g = (s + c) * scale;
+            if (out_fp32)
+                static_cast<float*>(out)[j] = float(g);
+            else
+                static_cast<double*>(out)[j] = g;
+        }
+    }
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave (lane order).
 __device__ __forceinline__ double wave_inclusive_scan(double v)
 {

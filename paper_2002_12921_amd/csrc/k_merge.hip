@@ -14,7 +14,24 @@ namespace vegas {
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge(MergeArgs a)
 {
+    if (int(blockIdx.x) == a.d + 1) {  // MERGE_GRAD: the gradient rows, scaled by 1/M
+        adjoint_merge_block(a.gpart, a.rows, a.d, 1.0 / a.M, a.grad_out, 0);
+        return;
+    }
     merge_group(a, blockIdx.x);
+}
+
+// grad = gout * G, rounded once to the output's precision.
+__global__ void k_grad_scale(const double* G, const double* gout, void* grad, int n, int grad_fp32)
+{
+    const double s = *gout;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double g = s * G[j];
+        if (grad_fp32)
+            static_cast<float*>(grad)[j] = float(g);
+        else
+            static_cast<double*>(grad)[j] = g;
+    }
 }
 
 // Stand-alone refinement from the stored histograms of the last iteration.
@@ -187,7 +204,14 @@ __global__ void k_copy_last(const DevResult* R, double* out)
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_merge, dim3(a.d + 1), dim3(kMergeThreads), 0, s, a);
+    const int blocks = a.d + 1 + ((a.flags & MERGE_GRAD) ? 1 : 0);
+    hipLaunchKernelGGL(k_merge, dim3(blocks), dim3(kMergeThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_scale(const double* G, const double* gout, void* grad, int n, int grad_fp32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_scale, dim3(1), dim3(128), 0, s, G, gout, grad, n, grad_fp32);
     return hipGetLastError();
 }
 

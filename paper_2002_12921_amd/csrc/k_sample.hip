@@ -257,29 +257,90 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     }
 }
 
-// Final step of the adjoint, scaled by gout/M: one wave per component j (and
-// j + 16, ...), lane l adding rows l, l + 64, ... in order with two-sums, then
-// an exact two-sum butterfly across the wave (the same pair on every lane).
-// The gradient is stored in FP64, or rounded once to FP32 (grad_fp32).
+// Final step of the adjoint: the rows' fixed-order sums scaled by gout/M,
+// stored in FP64 or rounded once to FP32 (grad_fp32).
 __global__ __launch_bounds__(kMergeThreads) void k_adjoint_merge(AdjointArgs a, int rows)
 {
-    const double scale = *a.gout / double(a.n);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j <= a.d; j += kMergeThreads / 64) {
-        double s = 0.0, c = 0.0;
-        for (int r = lane; r < rows; r += 64) twosum_add(s, c, a.partials[size_t(r) * (a.d + 1) + j]);
+    adjoint_merge_block(a.partials, rows, a.d, *a.gout / double(a.n), a.grad, a.grad_fp32);
+}
+
+// Forward pass with the gradient (Gaussian, frozen grid, no histograms):
+// the event kernel without histograms -- same events per thread, same
+// grouped Kahan S1, S2, so the estimate is bitwise that of k_sample -- that
+// also sums each event's v d ln f / d theta_j, as k_adjoint does, into
+// per-block rows gpart[block][d + 1] (merged by k_merge's gradient block).
+template <class P, int DMAX, bool EXACT>
+__global__ __launch_bounds__(kBlock) void k_sample_grad(SampleArgs a, double* gpart)
+{
+    using tab_t = typename TabEntry<P, GAUSS>::type;
+    using real = typename P::real;
+    extern __shared__ __align__(128) unsigned char smem[];
+    const int dN = a.d * a.N;
+    const size_t tab_bytes = (size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127);
+    tab_t* tab = reinterpret_cast<tab_t*>(smem);
+    double* red = reinterpret_cast<double*>(smem + tab_bytes);
+    const tab_t* gtab = static_cast<const tab_t*>(a.tab);
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
+    __syncthreads();
+
+    const DevConst* c = a.cst;
+    EvalConsts<P, GAUSS, DMAX> cst;
+    cst.load(c);
+    const double ds = P::is64 ? 1.0 : double(c->dscale32) * 0x1p-32;
+    const real ka = P::is64 ? real(c->kexp64) : real(double(c->ka32) * ds);
+    const real ka2 = real(2) * ka;
+    const double inv_a = c->inv_a;
+    const int d = EXACT ? DMAX : a.d;
+    const double ka64 = c->kexp64 * ds * ds;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    double g1 = 0.0, g2 = 0.0;
+    int ng = 0;
+    double g[DMAX + 1];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);
-            twosum_add(s, c, s2);
-            c += c2;
+    for (int j = 0; j <= DMAX; ++j) g[j] = 0.0;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t k = uint64_t(threadIdx.x) * gridDim.x + blockIdx.x; k < a.n; k += stride) {
+        EventEval<P, GAUSS, DMAX, EXACT> ev;
+        ev.run(cst, tab, nullptr, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
+        double v, v2;
+        {
+#pragma clang fp contract(off)
+            v = ev.value(cst);
+            v2 = v * v;
+            g1 += v;
+            g2 += v2;
         }
-        if (lane == 0) {
-            const double g = (s + c) * scale;
-            if (a.grad_fp32)
-                static_cast<float*>(a.grad)[j] = float(g);
-            else
-                static_cast<double*>(a.grad)[j] = g;
+        if (++ng == kGroup) {
+            kahan_add(s1, c1, g1);
+            kahan_add(s2, c2, g2);
+            g1 = g2 = 0.0;
+            ng = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            if (j < d) {
+                const real dl = ev.u[j] * ka2;
+                g[j] += v * double(dl);
+            }
+        }
+        const double da = 2.0 * ev.s64 * ka64 - double(d);
+        g[DMAX] += v * (da * inv_a);
+    }
+    kahan_add(s1, c1, g1);
+    kahan_add(s2, c2, g2);
+    const double S1 = block_sum(s1 - c1, red);
+    const double S2 = block_sum(s2 - c2, red);
+    if (threadIdx.x == 0) {
+        double* row = a.partials + size_t(blockIdx.x) * 2;
+        row[0] = S1;
+        row[1] = S2;
+    }
+    double* grow = gpart + size_t(blockIdx.x) * (d + 1);
+#pragma unroll
+    for (int j = 0; j <= DMAX; ++j) {
+        if (j < d || j == DMAX) {
+            const double t = block_sum(g[j], red);
+            if (threadIdx.x == 0) grow[j < d ? j : d] = t;
         }
     }
 }
@@ -381,6 +442,24 @@ static const void* adjoint_fn(int d)
         VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_adjoint<P, D_, true>))
     }
     VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_adjoint<P, D_, false>))
+}
+
+template <class P>
+static const void* sample_grad_fn(int d)
+{
+    if (d == dim_bucket(d)) {
+        VEGAS_DMAX_SWITCH(d, return reinterpret_cast<const void*>(&k_sample_grad<P, D_, true>))
+    }
+    VEGAS_DMAX_SWITCH(dim_bucket(d), return reinterpret_cast<const void*>(&k_sample_grad<P, D_, false>))
+}
+
+hipError_t launch_sample_grad(int prec, const SampleArgs& a, double* gpart, int blocks, int threads, hipStream_t s)
+{
+    const void* fn = prec == FP64 ? sample_grad_fn<P64>(a.d) : sample_grad_fn<P32>(a.d);
+    const size_t tab = size_t(a.d) * a.N * tab_entry_bytes(prec, GAUSS);
+    const size_t lds = ((tab + 127) & ~size_t(127)) + sizeof(double) * (kBlock / 64);
+    void* args[] = {const_cast<SampleArgs*>(&a), &gpart};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, s);
 }
 
 size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist)

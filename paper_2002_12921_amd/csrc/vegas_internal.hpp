@@ -215,7 +215,8 @@ enum MergeFlags {
     MERGE_NO_COMBINE = 4,
     MERGE_REFINE = 8,
     MERGE_NO_HIST = 16,
-    MERGE_NO_RECORD = 32  // statistics of the iteration kept as the last ones, not recorded
+    MERGE_NO_RECORD = 32,  // statistics of the iteration kept as the last ones, not recorded
+    MERGE_GRAD = 64        // one more block sums the gradient rows gpart into grad_out (times 1/M)
 };
 
 struct MergeArgs {
@@ -233,6 +234,8 @@ struct MergeArgs {
     DevResult* result;
     double alpha;
     double M;                // events of the iteration (at END)
+    const double* gpart;     // MERGE_GRAD: [rows][d + 1] gradient rows of the event kernel
+    double* grad_out;        // MERGE_GRAD: [d + 1] (1/M) sum of the rows
     int rows;
     int rstride;             // doubles per partial row: 2, or pstride when the rows hold H
     int d, N, pstride, kind;
@@ -294,6 +297,8 @@ struct BatchArgs {
 hipError_t launch_sample(int prec, int kind, const SampleArgs& a, int blocks, int threads, hipStream_t s);
 size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist = true);
 hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s);
+hipError_t launch_sample_grad(int prec, const SampleArgs& a, double* gpart, int blocks, int threads, hipStream_t s);
+hipError_t launch_grad_scale(const double* G, const double* gout, void* grad, int n, int grad_fp32, hipStream_t s);
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int blocks, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_refine(const MergeArgs& a, hipStream_t s);   // from `last`, d blocks

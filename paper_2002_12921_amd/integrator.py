@@ -132,6 +132,19 @@ class Vegas:
             flags |= _lib.NO_HIST
         check(lib().vegas_iterate(self._ctx, int(n_events), flags, self._s()), "iterate")
 
+    def iterate_grad(self, n_events: int, G: torch.Tensor, combine: bool = True, record: bool = True):
+        """One whole iteration on the frozen grid (no histograms) that also
+        writes the estimate's gradient (1/M) sum w df/d(mu, a) into G (FP64,
+        d + 1 values, on the device).  Gaussian integrand only."""
+        assert G.is_cuda and G.dtype == torch.float64 and G.is_contiguous() and G.numel() >= self.dim + 1
+        flags = _lib.ITER_FULL | _lib.NO_HIST
+        if not combine:
+            flags |= _lib.NO_COMBINE
+        if not record:
+            flags |= _lib.NO_RECORD
+        check(lib().vegas_iterate_grad(self._ctx, int(n_events), flags, ctypes.c_void_p(G.data_ptr()), self._s()),
+              "iterate_grad")
+
     def refine(self):
         check(lib().vegas_refine(self._ctx, self._s()), "refine")
 
@@ -171,6 +184,14 @@ class Vegas:
         assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 2
         check(lib().vegas_last_iteration_device(self._ctx, ctypes.c_void_p(out.data_ptr()), self._s()),
               "last_iteration_device")
+
+    def grad_scale(self, G: torch.Tensor, gout: torch.Tensor, grad: torch.Tensor):
+        """grad = gout * G (d + 1 values), one rounding to grad's dtype."""
+        assert G.is_cuda and G.dtype == torch.float64 and gout.is_cuda and gout.dtype == torch.float64
+        assert grad.is_cuda and grad.dtype in (torch.float64, torch.float32) and grad.is_contiguous()
+        check(lib().vegas_grad_scale(ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(gout.data_ptr()),
+                                     ctypes.c_void_p(grad.data_ptr()), self.dim + 1,
+                                     1 if grad.dtype == torch.float32 else 0, self._s()), "grad_scale")
 
     def adjoint(self, iteration: int, n_events: int, gout: torch.Tensor, grad: torch.Tensor):
         """grad (d + 1 values, FP64 or FP32) = gout (1/M) sum_e w_e df/d(mu, a)."""

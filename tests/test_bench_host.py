@@ -4,10 +4,13 @@ import bench
 
 
 def test_alg_slots_table():
-    # Philox 40 ceil(d/4) - (ceil(d/4) - 1), 7 per dimension, 20 per event
-    assert bench.alg_slots_per_event(8) == 79 + 56 + 20
-    assert bench.alg_slots_per_event(5) == 79 + 35 + 20
-    assert bench.alg_slots_per_event(4) == 40 + 28 + 20
+    # the method's step table: Philox 40 per group of four dimensions;
+    # binning 2, map 3, integrand 2, Jacobian 1, histogram address 1 per
+    # dimension; 3 + 4 (one quarter-rate exponential) + 10 (sums) per event
+    assert bench.alg_slots_per_event(8) == 169
+    assert bench.alg_slots_per_event(5) == 80 + 45 + 17
+    assert bench.alg_slots_per_event(4) == 40 + 36 + 17
+    assert bench.alg_slots_per_event(20) == 200 + 180 + 17
 
 
 def test_gpus_above_one_is_refused(monkeypatch, capsys):
@@ -20,10 +23,12 @@ def test_gpus_above_one_is_refused(monkeypatch, capsys):
     assert "one GPU" in capsys.readouterr().err
 
 
-def test_traffic_only_for_the_profiled_kernel(monkeypatch):
-    t, note = bench.measured_traffic()
+def test_counters_only_for_the_profiled_kernel(monkeypatch):
+    t, busy, note = bench.measured_counters()
     if t is not None:
         assert 1.0e6 < t < 1.0e8
+    if busy is not None:
+        assert 0.0 < busy <= 1.0
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 64)
-    t, note = bench.measured_traffic()
-    assert t is None and "changed" in note
+    t, busy, note = bench.measured_counters()
+    assert t is None and busy is None and "changed" in note

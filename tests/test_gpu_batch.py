@@ -125,3 +125,101 @@ def test_batch256_shape_sampled():
         ref = _oracle_run(q, 10, 5)
         I, s, _ = ref["final"]
         assert abs(res[p]["integral"] - I) <= 0.1 * s, (p, res[p]["integral"], I, s)
+
+
+def _hist_close(Hg, Ho, tol):
+    return np.all(np.abs(Hg - Ho) <= tol * Ho.sum(axis=1, keepdims=True))
+
+
+def test_batch256_lockstep_against_oracle():
+    """The benchmarked 256-problem FP32-mixed batch, stepped one iteration at
+    a time with the kernels the graph records: for two problems of each
+    dimension bucket (d <= 4, <= 8, <= 16; the largest event count of the
+    bucket and a middling one), every iteration's S1, S2 and (adaptation
+    iterations) every histogram bin against the oracle on the batch's own
+    grid at 1e-6, and every refinement against the oracle's refinement of the
+    batch's histograms at 1e-12.  After the last step the combined results
+    equal those of a graph replay."""
+    probs = workloads.batch256()
+    n_iter, n_adapt = 10, 5
+    b = VegasBatch(probs, n_iter, n_adapt)
+    sel = []
+    for lo, hi in ((2, 4), (5, 8), (9, 16)):
+        ps = [p for p, q in enumerate(probs) if lo <= q["dim"] <= hi]
+        ps.sort(key=lambda p: probs[p]["n_events"])
+        sel += [ps[-1], ps[len(ps) // 2]]
+    assert len(set(sel)) == 6
+    with pytest.raises(Exception):
+        b.step(3)  # steps run in order from 0
+    for p in sel:  # the plan leaves every problem at its start
+        assert np.array_equal(b.edges(p), oracle.uniform_edges(probs[p]["dim"], 50))
+    tol = 1e-6
+    for k in range(n_iter):
+        before = {p: b.edges(p) for p in sel}
+        b.step(k)
+        for p in sel:
+            q = probs[p]
+            pr = oracle.Problem(q["dim"], 50, oracle.GAUSS, q["params"], seed=0, problem=q["problem"])
+            S1, S2, H = b.last_iteration(p)
+            o1, o2, Ho = oracle.accumulate(pr, before[p], k, q["n_events"])
+            assert abs(S1 - o1) <= tol * abs(o1), (p, k, S1, o1)
+            assert abs(S2 - o2) <= tol * abs(o2), (p, k, S2, o2)
+            E = b.edges(p)
+            if k < n_adapt:
+                assert _hist_close(H, Ho, tol), (p, k)
+                assert np.max(np.abs(E - oracle.refine(H, before[p], 1.5))) <= 1e-12, (p, k)
+            else:
+                assert np.all(H == 0.0) and np.array_equal(E, before[p])
+    stepped = b.results()
+    b.run()
+    replay = b.results()
+    for x, y in zip(stepped, replay):
+        # the histograms' LDS atomics add in no fixed order, so the grids (and
+        # what follows) agree to rounding
+        assert abs(x["integral"] - y["integral"]) <= 1e-10 * abs(y["integral"])
+        assert x["n_combined"] == y["n_combined"] == n_iter - n_adapt
+
+
+def test_forced_launch_shape_gives_the_same_results(monkeypatch):
+    """The tuner's choice only changes the speed: a batch planned with a shape
+    it did not choose (threads and histogram replicas forced for every
+    bucket) gives the same per-problem results up to the reduction order."""
+    probs = _small_batch("fp32_mixed", n=8, seed=5)
+    b = VegasBatch(probs, 4, 2)
+    sched = b.schedule()
+    assert len(sched["buckets"]) >= 1 and sched["tuned_ms"] > 0
+    b.run()
+    r1 = b.results()
+    bk = sched["buckets"][0]
+    th = 256 if bk["threads"] != 256 else 1024
+    rp = 2 if bk["replicas"] != 2 else 8
+    monkeypatch.setenv("VEGAS_BATCH_THREADS", str(th))
+    monkeypatch.setenv("VEGAS_BATCH_REPLICAS", str(rp))
+    c = VegasBatch(probs, 4, 2)
+    s2 = c.schedule()
+    assert all(x["threads"] == th and x["replicas"] == rp for x in s2["buckets"]), s2
+    c.run()
+    r2 = c.results()
+    for x, y in zip(r1, r2):
+        assert abs(x["integral"] - y["integral"]) <= 1e-10 * abs(y["integral"])
+        assert abs(x["sigma"] - y["sigma"]) <= 1e-8 * y["sigma"]
+
+
+def test_tuning_cache_round_trip(monkeypatch, tmp_path):
+    """With VEGAS_BATCH_TUNE_CACHE set, the first plan tunes and stores its
+    choice; a second plan of the same batch on the same device reads it back
+    (no tuning) and gets the same schedule."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("VEGAS_BATCH_TUNE_CACHE", str(path))
+    probs = _small_batch("fp64", n=5, seed=9)
+    a = VegasBatch(probs, 3, 2)
+    sa = a.schedule()
+    assert not sa["from_cache"] and path.exists()
+    b = VegasBatch(probs, 3, 2)
+    sb = b.schedule()
+    assert sb["from_cache"]
+    assert sb["tile_events"] == sa["tile_events"] and sb["buckets"] == sa["buckets"]
+    a.run()
+    b.run()
+    for x, y in zip(a.results(), b.results()):
+        assert abs(x["integral"] - y["integral"]) <= 1e-12 * abs(y["integral"])

@@ -370,9 +370,13 @@ def test_small_and_ragged_sizes(M):
 
 
 def _tol(prec, d):
-    """1e-12 for FP64; 1e-6 for FP32-mixed up to d = 8, growing like d beyond
-    (the FP32 rounding of the exponent, a sum of d terms, grows with d)."""
-    return 1e-12 if prec == "fp64" else 1e-6 * max(1.0, d / 8)
+    """1e-12 for FP64; 1e-6 for FP32-mixed up to d = 20 (every benchmarked
+    case).  Beyond, the rounding of the FP32 map and exponent, summed over d
+    dimensions, grows with d (a = 0.3 at d = 33 puts S2 2.6e-6 from the
+    oracle): 1e-6 d/8 there."""
+    if prec == "fp64":
+        return 1e-12
+    return 1e-6 if d <= 20 else 1e-6 * d / 8
 
 
 @pytest.mark.parametrize("d,N,prec", [(1, 2, "fp64"), (64, 50, "fp64"), (64, 100, "fp32_mixed"),
@@ -570,11 +574,13 @@ def test_autograd_function(dtype):
     assert gm[0] > 0.3
 
 
-def test_autograd_two_forwards_one_backward():
+@pytest.mark.parametrize("fused", [True, False])
+def test_autograd_two_forwards_one_backward(fused):
     """Two forward passes on one context at different centres, then one
     backward of their sum: each gradient is the adjoint at its own centre and
-    iteration (the backward sets the forward's parameters back), and the
-    context's parameters afterwards are the last ones set."""
+    iteration (fused: summed in the forward launch; else the backward sets
+    the forward's parameters back for the adjoint kernel), and the context's
+    parameters afterwards are the last ones set."""
     from paper_2002_12921_amd.autograd import vegas_integral
     d, N, M = 4, 40, 100_000
     mu1_h = np.array([0.15, 0.45, 0.5, 0.62], dtype=np.float32)
@@ -588,9 +594,9 @@ def test_autograd_two_forwards_one_backward():
     mu1 = torch.tensor(mu1_h, device="cuda", requires_grad=True)
     mu2 = torch.tensor(mu2_h, device="cuda", requires_grad=True)
     t1 = v.iteration_index
-    I1 = vegas_integral(mu1, a, v, M)
+    I1 = vegas_integral(mu1, a, v, M, fused)
     t2 = v.iteration_index
-    I2 = vegas_integral(mu2, a, v, M)
+    I2 = vegas_integral(mu2, a, v, M, fused)
     assert t2 == t1 + 1
     (2.0 * I1 + 3.0 * I2).backward()
     ga = 0.0
@@ -610,22 +616,33 @@ def test_autograd_two_forwards_one_backward():
     assert v.result(allow_nonfinite=True)["n_iter"] == 3
 
 
-def test_autograd_backward_after_refine_raises():
-    """A refinement between forward and backward changes the grid the adjoint
-    would use: backward refuses."""
+@pytest.mark.parametrize("fused", [True, False])
+def test_autograd_backward_after_refine(fused):
+    """A refinement between forward and backward changes the grid: the
+    separate adjoint pass would need the old one, so its backward refuses;
+    the fused gradient was summed at the forward's grid and stays valid."""
     from paper_2002_12921_amd.autograd import vegas_integral
-    d = 3
-    v = Vegas(d, 20, "gauss", [0.1] + [0.5] * d, "fp64")
+    d, N, M = 3, 20, 10_000
+    v = Vegas(d, N, "gauss", [0.1] + [0.5] * d, "fp64")
     v.iterate(20_000, refine=True)
+    E = v.edges()
     mu = torch.full((d,), 0.5, dtype=torch.float64, device="cuda", requires_grad=True)
     a = torch.tensor(0.1, dtype=torch.float64, device="cuda", requires_grad=True)
-    I = vegas_integral(mu, a, v, 10_000)
+    t = v.iteration_index
+    I = vegas_integral(mu, a, v, M, fused)
     v.iterate(20_000, refine=True)
-    with pytest.raises(RuntimeError, match="grid changed"):
-        I.backward()
+    if not fused:
+        with pytest.raises(RuntimeError, match="grid changed"):
+            I.backward()
+        return
+    I.backward()
+    G, Gabs = oracle.adjoint(oracle.Problem(d, N, oracle.GAUSS, [0.1] + [0.5] * d), E, t, M)
+    assert np.all(np.abs(mu.grad.cpu().numpy() - G[:d] / M) <= 1e-12 * Gabs[:d] / M)
+    assert abs(float(a.grad.cpu()) - G[d] / M) <= 1e-12 * Gabs[d] / M
 
 
-def test_autograd_many_forward_passes():
+@pytest.mark.parametrize("fused", [True, False])
+def test_autograd_many_forward_passes(fused):
     """More forward passes than a context has record slots (1024): none of
     them takes a slot, and a backward after them still matches the oracle."""
     from paper_2002_12921_amd.autograd import vegas_integral
@@ -634,7 +651,7 @@ def test_autograd_many_forward_passes():
     mu = torch.tensor([0.4, 0.6], dtype=torch.float64, device="cuda", requires_grad=True)
     a = torch.tensor(0.2, dtype=torch.float64, device="cuda", requires_grad=True)
     for _ in range(1100):
-        I = vegas_integral(mu, a, v, M)
+        I = vegas_integral(mu, a, v, M, fused)
     t = v.iteration_index - 1
     I.backward()
     pr = oracle.Problem(d, N, oracle.GAUSS, [0.2, 0.4, 0.6])
@@ -645,6 +662,62 @@ def test_autograd_many_forward_passes():
     # recorded iterations still work after them
     v.iterate(M)
     assert v.result()["n_iter"] == 1
+
+
+@pytest.mark.parametrize("d", [8, 5, 12])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_fused_gradient_matches_oracle(prec, d):
+    """The forward pass with the gradient (vegas_iterate_grad): its estimate is
+    bitwise that of the plain frozen-grid iteration (same events, same sums),
+    and its gradient matches the oracle's per-sample analytic gradient at the
+    same points and grid, at the path's tolerance relative to the L1 size of
+    the terms (as the separate adjoint kernel)."""
+    N, M, t = 50, 300_000, 0
+    tol = _tol(prec, d)
+    mu = np.random.default_rng(1).uniform(0.3, 0.7, d).astype(np.float32)
+    params = [0.1] + [float(m) for m in mu]
+    E = _adapted_edges(d, N, params)
+    v = Vegas(d, N, "gauss", params, prec)
+    v.set_edges(E)
+    w = Vegas(d, N, "gauss", params, prec)
+    w.set_edges(E)
+    G = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
+    v.iterate_grad(M, G)
+    w.iterate(M, hist=False)
+    s1v, s2v, _ = v.last_iteration()
+    s1w, s2w, _ = w.last_iteration()
+    assert s1v == s1w and s2v == s2w
+    o1, _, _ = oracle.accumulate(oracle.Problem(d, N, oracle.GAUSS, params), E, t, M)
+    assert abs(s1v - o1) <= tol * o1
+    Go, Gabs = oracle.adjoint(oracle.Problem(d, N, oracle.GAUSS, params), E, t, M)
+    assert np.all(np.abs(G.cpu().numpy() - Go / M) <= tol * Gabs / M)
+    # backward: gout times G, rounded once
+    gout = torch.full((1,), 0.75, dtype=torch.float64, device="cuda")
+    g32 = torch.zeros(d + 1, dtype=torch.float32, device="cuda")
+    v.grad_scale(G, gout, g32)
+    assert np.array_equal(g32.cpu().numpy(), (0.75 * G.cpu().numpy()).astype(np.float32))
+
+
+def test_fused_gradient_c4_shape():
+    """The differentiable case as benchmarked (the fused forward): d = 8,
+    FP32 centres mu ~ U[0.3, 0.7] (seed 0), a = 0.1, grid from 5 FP64
+    adaptation iterations of 1e6 events, 1e7 events at iteration 5 in
+    FP32-mixed, against the oracle's analytic gradient at the same points."""
+    d, N, M = 8, 50, 10_000_000
+    mu32 = np.random.default_rng(0).uniform(0.3, 0.7, d).astype(np.float32)
+    params = [float(np.float32(0.1))] + [float(m) for m in mu32]
+    ad = Vegas(d, N, "gauss", params, "fp64")
+    for _ in range(5):
+        ad.iterate(1_000_000, refine=True)
+    E = ad.edges()
+    v = Vegas(d, N, "gauss", params, "fp32_mixed")
+    v.set_edges(E)
+    for _ in range(5):
+        v.iterate(10, hist=False, record=False)  # to iteration index 5
+    G = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
+    v.iterate_grad(M, G, combine=False, record=False)
+    Go, Gabs = oracle.adjoint(oracle.Problem(d, N, oracle.GAUSS, params), E, 5, M)
+    assert np.all(np.abs(G.cpu().numpy() - Go / M) <= 1e-6 * Gabs / M)
 
 
 def test_adjoint_fp32_output_is_rounded_fp64():
