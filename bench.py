@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 # worker processes of the CPU baseline (at most; the host's cores otherwise)
 CPU_WORKERS = 12
+# untimed event-kernel launches (about 0.1 s of load) before a timed path
+CLOCK_WARM_LAUNCHES = 2000
 METRIC = "events/s per Vegas iteration (d=8 Gaussian, 1e7 evts), FP32-mixed vs FP64"
 D, NBINS, A, ALPHA, EVENTS = 8, 50, 0.1, 1.5, 10_000_000
 
@@ -149,6 +151,12 @@ def time_path(precision: str, steps: int, warmup: int, blocks: int = 0, replicas
     if replicas:
         v.set_hist_replicas(replicas)
     stream = torch.cuda.current_stream()
+    # The GPU's clock drops within half a second of idle and comes back after
+    # tens of milliseconds of sustained load: a step measured straight after
+    # idle takes ~56 us instead of ~48.  So the event kernel first runs for
+    # about 0.1 s, untimed (it leaves the context's state as it was), before
+    # the warm-up steps and the timed ones.
+    v.time_event_kernel(EVENTS, CLOCK_WARM_LAUNCHES)
     for k in range(warmup):
         v.iterate(EVENTS, refine=True, combine=False)
         if k % 1000 == 999:
@@ -586,6 +594,63 @@ def issue_probe():
     return out
 
 
+def profile_legs():
+    """Short runs of every benchmarked kernel, for rocprofv3 (traces and
+    counters): the issue probe; the d = 8 Gaussian in both precisions (10
+    adaptation steps, 5 accumulation iterations); the d = 20 bimodal (one
+    adaptation and one accumulation iteration, each 10 chunks of 1e7); the
+    Genz integrands at d = 16 (3 adaptation steps per kind and precision);
+    the 256-problem batch (one graph replay; the plan reads its schedule from
+    VEGAS_BATCH_TUNE_CACHE when set, so no tuning launches are traced); the
+    differentiable d = 8 case (5 fused forward + backward passes, 3 separate
+    adjoints); the d = 8 Gaussian as a user integrand (3 adaptation steps per
+    precision); and the 256 MiB copy that scales the HBM counters."""
+    import torch
+    from paper_2002_12921_amd import Vegas, workloads
+    from paper_2002_12921_amd.autograd import vegas_integral
+    from paper_2002_12921_amd.batch import VegasBatch
+
+    issue_probe()
+    for prec in ("fp32_mixed", "fp64"):
+        v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, prec, seed=0, alpha=ALPHA)
+        for _ in range(10):
+            v.iterate(EVENTS, refine=True, combine=False)
+        for _ in range(5):
+            v.iterate(EVENTS, hist=False)
+    v = Vegas(20, 100, "bimodal", workloads.bimodal20(), "fp32_mixed", seed=0, alpha=ALPHA)
+    for adapt in (True, False):
+        for k in range(10):
+            ch = "begin" if k == 0 else ("end" if k == 9 else "mid")
+            v.iterate(EVENTS, chunk=ch, refine=adapt, combine=not adapt, hist=adapt)
+    for kind in ("genz_disc", "genz_peak"):
+        for prec in ("fp32_mixed", "fp64"):
+            v = Vegas(16, NBINS, kind, workloads.genz16(kind), prec, seed=0, alpha=ALPHA)
+            for _ in range(3):
+                v.iterate(EVENTS, refine=True, combine=False)
+    b = VegasBatch(workloads.batch256(), 10, 5)
+    b.run()
+    torch.cuda.synchronize()
+    b.close()
+    mu0, a0 = workloads.c4_params()
+    v = Vegas(D, NBINS, "gauss", [float(a0)] + [float(m) for m in mu0], "fp32_mixed", seed=0, alpha=ALPHA)
+    for _ in range(5):
+        v.iterate(1_000_000, refine=True, combine=False)
+    mu = torch.tensor(mu0, device="cuda", requires_grad=True)
+    a = torch.tensor(a0, device="cuda", requires_grad=True)
+    for _ in range(5):
+        vegas_integral(mu, a, v, EVENTS).backward()
+    for _ in range(3):
+        vegas_integral(mu, a, v, EVENTS, False).backward()
+    from paper_2002_12921_amd import user_integrands
+    for prec in ("fp64", "fp32_mixed"):
+        v = Vegas(D, NBINS, params=[A] + [0.5] * D, source=user_integrands.GAUSSIAN, precision=prec, seed=0,
+                  alpha=ALPHA)
+        for _ in range(3):
+            v.iterate(EVENTS, refine=True, combine=False)
+    copy_probe()
+    torch.cuda.synchronize()
+
+
 def copy_probe():
     """A plain device copy of known size (256 MiB), used to scale the HBM
     counters of a profiled run."""
@@ -612,6 +677,8 @@ def main():
     ap.add_argument("--fp64-only", action="store_true",
                     help="only time the FP64 adaptation step (for profiling the FP64 event kernel)")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--profile-legs", action="store_true",
+                    help="only run every benchmarked kernel briefly (for rocprofv3)")
     ap.add_argument("--issue-probe", action="store_true",
                     help="only run the VALU issue-rate probe")
     ap.add_argument("--phase-split", action="store_true",
@@ -628,7 +695,8 @@ def main():
 
     # the CPU baseline's worker processes start before anything touches the GPU
     pool, workers = None, 0
-    if not (args.no_cpu_baseline or args.copy_probe or args.phase_split or args.fp64_only or args.issue_probe):
+    if not (args.no_cpu_baseline or args.copy_probe or args.phase_split or args.fp64_only or args.issue_probe
+            or args.profile_legs):
         import multiprocessing as mp
         workers = max(1, min(len(os.sched_getaffinity(0)), CPU_WORKERS))
         pool = mp.get_context("spawn").Pool(workers)
@@ -644,12 +712,20 @@ def main():
     if args.issue_probe:
         print(json.dumps({"issue_probe": issue_probe()}), flush=True)
         return
+    if args.profile_legs:
+        profile_legs()
+        print(json.dumps({"profile_legs": "done"}), flush=True)
+        return
     if args.fp64_only:
         r = time_path("fp64", args.steps, args.warmup)
         print(json.dumps({"fp64_only": {k: r[k] for k in ("ms_per_step", "events_per_s", "event_kernel_ms")}}),
               flush=True)
         return
 
+    # the issue probe first: ~40 ms of sustained load, which also brings the
+    # GPU's clock up before the headline (a cold clock runs the first tens of
+    # milliseconds of load ~15 % slower)
+    probe = None if args.mixed_only else issue_probe()
     mixed = time_path("fp32_mixed", args.steps, args.warmup)
     fp64 = None if args.mixed_only else time_path("fp64", args.steps, args.warmup)
     sched = {} if args.mixed_only else {p: c2_schedule(p) for p in ("fp32_mixed", "fp64")}
@@ -733,8 +809,8 @@ def main():
                 "event_kernel_ms": u["event_kernel_ms"], "launch": u["launch"],
                 "compile_and_init_s": u["init_s"],
                 "over_builtin": u["events_per_s"] / builtin["events_per_s"] if builtin else None}
-    if not args.mixed_only:
-        out["issue_probe"] = issue_probe()
+    if probe is not None:
+        out["issue_probe"] = probe
     if pool is not None:
         lock = {"fp32_mixed": mixed["lockstep"]}
         if fp64 is not None:

@@ -217,6 +217,16 @@ vegas_status vegas_iterate(vegas_ctx* ctx, int64_t n_events, uint32_t flags,
 vegas_status vegas_iterate_grad(vegas_ctx* ctx, int64_t n_events, uint32_t flags, double* dev_G,
                                 vegas_stream_t stream);
 
+/* The whole forward pass of a differentiable estimate in one call (for
+ * training loops, where every host call costs): vegas_set_params_device
+ * (dev_params, n_params, is_fp32), then vegas_iterate_grad(n_events, flags,
+ * dev_G), whose reduction also writes (I_t, sigma_t) of the iteration to
+ * dev_out2[2] (device FP64).  Gaussian integrand; flags as for
+ * vegas_iterate_grad.  Arguments are checked before anything is launched. */
+vegas_status vegas_forward_grad(vegas_ctx* ctx, const void* dev_params, int32_t n_params, int32_t is_fp32,
+                                int64_t n_events, uint32_t flags, double* dev_G, double* dev_out2,
+                                vegas_stream_t stream);
+
 /* dev_grad[j] = (*dev_gout) * dev_G[j], j < n (1 <= n <= 65), each rounded
  * once to FP64 or (grad_fp32) FP32; all pointers device memory. */
 vegas_status vegas_grad_scale(const double* dev_G, const double* dev_gout, void* dev_grad, int32_t n,

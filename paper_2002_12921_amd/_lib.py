@@ -26,7 +26,7 @@ CHUNK_BEGIN, CHUNK_END, ITER_FULL, NO_COMBINE, REFINE, NO_HIST, NO_RECORD = 1, 2
 # every symbol include/vegas.h declares
 EXPORTS = [
     "vegas_workspace_size", "vegas_init_grid", "vegas_init_grid_noalloc", "vegas_init_user", "vegas_user_compile", "vegas_iterate",
-    "vegas_iterate_grad", "vegas_grad_scale", "vegas_refine", "vegas_result",
+    "vegas_iterate_grad", "vegas_forward_grad", "vegas_grad_scale", "vegas_refine", "vegas_result",
     "vegas_reset_results", "vegas_set_params_device", "vegas_get_params_device", "vegas_get_versions",
     "vegas_last_iteration_device",
     "vegas_adjoint", "vegas_dump_events", "vegas_get_edges", "vegas_set_edges",
@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
         "vegas_user_compile": [ctypes.c_char_p, i32, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],
         "vegas_iterate_grad": [vp, i64, u32, vp, vp],
+        "vegas_forward_grad": [vp, vp, i32, i32, i64, u32, vp, vp, vp],
         "vegas_grad_scale": [vp, vp, vp, i32, i32, vp],
         "vegas_refine": [vp, vp],
         "vegas_result": [vp, P(Result), vp],

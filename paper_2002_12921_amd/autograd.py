@@ -37,24 +37,25 @@ class VegasIntegral(torch.autograd.Function):
         # parameters go to the library as they are (it widens them, exactly)
         pt = torch.float32 if mu.dtype == torch.float32 and a.dtype == torch.float32 else torch.float64
         params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
-        vegas.set_params_device(params)
-        t = vegas.iteration_index
         out = torch.empty(2, dtype=torch.float64, device=mu.device)
         ctx.G = None
         if fused:
-            # frozen grid: no histograms, no record slot; the gradient terms
-            # are summed in the same launch
+            # one library call: the parameters, then the frozen-grid iteration
+            # (no histograms, no record slot) whose launch also sums the
+            # gradient terms, its (I_t, sigma_t) written to out
             G = torch.empty(d + 1, dtype=torch.float64, device=mu.device)
-            vegas.iterate_grad(n_events, G, combine=False, record=False)
+            vegas.forward_grad(params, n_events, G, out)
             ctx.G = G
         else:
+            vegas.set_params_device(params)
+            ctx.t = vegas.iteration_index
             # frozen grid: no histograms (the sums are bitwise those of the
             # histogram variant) and no record slot
             vegas.iterate(n_events, refine=False, combine=False, hist=False, record=False)
+            vegas.last_iteration_device(out)
             ctx.params = params  # a tensor of its own: nothing else writes it
             ctx.versions = vegas.versions()
-        vegas.last_iteration_device(out)
-        ctx.vegas, ctx.t, ctx.n = vegas, t, n_events
+        ctx.vegas, ctx.n = vegas, n_events
         ctx.mu_meta = (mu.dtype, mu.shape)
         ctx.a_meta = (a.dtype, a.shape)
         return out[0]

@@ -25,6 +25,7 @@ constexpr int kBatchMaxIter = 1024;
 constexpr int kMaxProblems = 65535;
 const uint64_t kTileCandidates[] = {1u << 13, 1u << 14, 1u << 15, 1u << 16, 1u << 17};
 constexpr uint64_t kTileMin = 1u << 13;
+constexpr int kTuneWarmRuns = 3;  // untimed schedule timings before the tuning's own
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -555,38 +556,45 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         if ((he = tm.init(2 * int(b->buckets.size()))) != hipSuccess)
             return bail(fail(VEGAS_EHIP, "hipEventCreate: %s", hipGetErrorString(he)));
         std::vector<double> per;
+        // The GPU's clock ramps up over the first tens of milliseconds of
+        // sustained load, and a timing taken early reads slow.  So the
+        // tuning starts with untimed runs of the starting schedule, and every
+        // candidate is timed in two round-robin passes, keeping its faster
+        // time: drift over the passes then touches every candidate alike.
+        if ((st = upload_schedule(b, tile ? tile : kTileCandidates[2])) != VEGAS_OK) return bail(st);
+        for (int w = 0; w < kTuneWarmRuns; ++w)
+            if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+        auto total = [](const std::vector<double>& v) {
+            double t = 0.0;
+            for (double x : v) t += x;
+            return t;
+        };
         if (!tile) {
-            double best_ms = 1e300;
-            for (uint64_t T : kTileCandidates) {
-                if ((st = upload_schedule(b, T)) != VEGAS_OK) return bail(st);
-                if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
-                double tot = 0.0;
-                for (double x : per) tot += x;
-                if (tot < best_ms) {
-                    best_ms = tot;
-                    tile = T;
+            const size_t nt = sizeof(kTileCandidates) / sizeof(kTileCandidates[0]);
+            std::vector<double> best_t(nt, 1e300);
+            for (int pass = 0; pass < 2; ++pass)
+                for (size_t c = 0; c < nt; ++c) {
+                    if ((st = upload_schedule(b, kTileCandidates[c])) != VEGAS_OK) return bail(st);
+                    if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+                    best_t[c] = std::min(best_t[c], total(per));
                 }
-            }
+            tile = kTileCandidates[std::min_element(best_t.begin(), best_t.end()) - best_t.begin()];
         }
         if ((st = upload_schedule(b, tile)) != VEGAS_OK) return bail(st);
-        if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
-        for (size_t q = 0; q < b->buckets.size(); ++q) b->buckets[q].tuned_ms = per[q];
         // each bucket's launch is timed on its own, so the buckets are tuned
         // one after another, each keeping its fastest shape
         for (size_t q = 0; q < b->buckets.size(); ++q) {
             auto& bk = b->buckets[q];
-            const vegas_batch::Bucket start = bk;
-            vegas_batch::Bucket best_bk = bk;
-            for (const Shape& sh : shapes[q]) {
-                if (sh.threads == start.threads && sh.l2 == start.hrep_log2) continue;
-                apply_shape(bk, sh);
-                if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
-                if (per[q] < best_bk.tuned_ms) {
-                    best_bk = bk;
-                    best_bk.tuned_ms = per[q];
+            std::vector<double> best_s(shapes[q].size(), 1e300);
+            for (int pass = 0; pass < 2; ++pass)
+                for (size_t c = 0; c < shapes[q].size(); ++c) {
+                    apply_shape(bk, shapes[q][c]);
+                    if ((st = time_schedule(b, tm, per)) != VEGAS_OK) return bail(st);
+                    best_s[c] = std::min(best_s[c], per[q]);
                 }
-            }
-            bk = best_bk;
+            const size_t c = size_t(std::min_element(best_s.begin(), best_s.end()) - best_s.begin());
+            apply_shape(bk, shapes[q][c]);
+            bk.tuned_ms = best_s[c];
         }
         if (cache_path && !any_forced) write_tuned(cache_path, key, b, tile);
         // the timed iterations refined grids and recorded iterations: every

@@ -477,8 +477,10 @@ vegas_status vegas_user_compile(const char* source, int32_t dim, int32_t precisi
 namespace {
 
 // vegas_iterate, and with dev_G (vegas_iterate_grad) the forward pass that
-// also forms the estimate's gradient into dev_G.
-vegas_status iterate_impl(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, vegas_stream_t stream)
+// also forms the estimate's gradient into dev_G; dev_out2 (optional): the
+// reduction also writes (I_t, sigma_t) there.
+vegas_status iterate_impl(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, double* dev_out2,
+                          vegas_stream_t stream)
 {
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40] (got %lld)", (long long)n);
@@ -526,6 +528,7 @@ vegas_status iterate_impl(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G
     MergeArgs ma = merge_args(c, blocks, mf, double(M));
     ma.gpart = c->P.adj_part;
     ma.grad_out = dev_G;
+    ma.last_out = dev_out2;
     VEGAS_HIP(launch_merge(ma, s));
     if (timed) {
         VEGAS_HIP(hipEventRecord(c->tev[3 * c->n_timed + 2], s));
@@ -552,13 +555,35 @@ extern "C" {
 
 vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
 {
-    return iterate_impl(c, n, flags, nullptr, stream);
+    return iterate_impl(c, n, flags, nullptr, nullptr, stream);
 }
 
 vegas_status vegas_iterate_grad(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, vegas_stream_t stream)
 {
     if (!dev_G) return fail(VEGAS_EINVAL, "dev_G is NULL");
-    return iterate_impl(c, n, flags, dev_G, stream);
+    return iterate_impl(c, n, flags, dev_G, nullptr, stream);
+}
+
+vegas_status vegas_forward_grad(vegas_ctx* c, const void* dev_params, int32_t n_params, int32_t is_fp32,
+                                int64_t n, uint32_t flags, double* dev_G, double* dev_out2, vegas_stream_t stream)
+{
+    if (!c || !dev_params || !dev_G || !dev_out2) return fail(VEGAS_EINVAL, "NULL argument");
+    if (c->kind != VEGAS_GAUSS) return fail(VEGAS_EUNSUPPORTED, "the gradient is implemented for the Gaussian integrand");
+    if (n_params != expected_params(c->kind, c->d)) return fail(VEGAS_EINVAL, "expected %d params, got %d",
+                                                               expected_params(c->kind, c->d), n_params);
+    if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    // the iteration's checks first, so that a refused call changes nothing
+    if (n < 2 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [2, 2^40]");
+    if ((flags & (VEGAS_ITER_FULL | VEGAS_NO_HIST)) != (VEGAS_ITER_FULL | VEGAS_NO_HIST) ||
+        (flags & ~uint32_t(VEGAS_ITER_FULL | VEGAS_NO_HIST | VEGAS_NO_COMBINE | VEGAS_NO_RECORD)))
+        return fail(VEGAS_EINVAL, "flags must be VEGAS_ITER_FULL | VEGAS_NO_HIST, optionally with NO_COMBINE, NO_RECORD");
+    if (!(flags & VEGAS_NO_RECORD) && c->rec_idx >= kMaxRecords)
+        return fail(VEGAS_ESTATE, "%d iterations recorded: call vegas_reset_results", kMaxRecords);
+    if (c->t >= (int64_t(1) << 32)) return fail(VEGAS_ESTATE, "iteration index exhausted");
+    VEGAS_HIP(launch_set_params(c->prec, c->kind, c->d, c->N, dev_params, n_params, is_fp32 ? 1 : 0, c->P,
+                                static_cast<hipStream_t>(stream)));
+    c->params_version += 1;
+    return iterate_impl(c, n, flags, dev_G, dev_out2, stream);
 }
 
 vegas_status vegas_grad_scale(const double* dev_G, const double* dev_gout, void* dev_grad, int32_t n,

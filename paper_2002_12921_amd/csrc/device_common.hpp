@@ -209,15 +209,27 @@ struct EventEval {
         for (int g = 0; g < DMAX / 4; ++g) {
             if (4 * g < d) {
                 const U4 k = philox4x32_10(elo, ehi, t, ctr3 + uint32_t(g), key0, key1);
+                // the group's four bins and table entries first, so that its
+                // LDS reads are in flight together before any is used
+                int bq[4];
+                uint32_t loq[4];
+                tab_t tq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int i = 4 * g + q;
                     if (i < d) {
-                        int bi;
-                        uint32_t lo;
-                        bin_words(k.w[q], c.bc, bi, lo);
+                        bin_words(k.w[q], c.bc, bq[q], loq[q]);
+                        tq[q] = (tab + i * N)[bq[q]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * g + q;
+                    if (i < d) {
+                        const int bi = bq[q];
+                        const uint32_t lo = loq[q];
                         b[i] = bi;
-                        const tab_t tb = (tab + i * N)[bi];
+                        const tab_t tb = tq[q];
                         real ui, ubi = real(0), width;
                         real dl;
                         if constexpr (P::is64) {

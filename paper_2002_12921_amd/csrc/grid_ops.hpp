@@ -16,6 +16,10 @@ __device__ static void finish_iteration(const MergeArgs& a, double S1, double S2
     const double I = S1 / M;
     const double var = (S2 / M - I * I) / (M - 1.0);
     const bool ok = isfinite(I) && isfinite(var);
+    if (a.last_out) {
+        a.last_out[0] = I;
+        a.last_out[1] = sqrt(var);
+    }
     DevResult* R = a.result;
     if (a.flags & MERGE_NO_RECORD) {
         R->last_integral = I;

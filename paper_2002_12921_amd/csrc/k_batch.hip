@@ -13,13 +13,14 @@
 
 namespace vegas {
 
-// Fewest waves per SIMD the register allocation must allow: 6 for the
-// FP32-mixed kernel of the d <= 16 bucket (80 VGPRs, a few spilled; it then
-// runs 512-thread blocks, 3 per CU, instead of one 1024-thread block, and the
-// 256-problem batch gains ~5 %), 4 elsewhere.
+// Fewest waves per SIMD the register allocation must allow: 4, i.e. up to
+// 128 registers.  The FP32-mixed kernel of the d <= 16 bucket needs about
+// 100; capped at 80 (6 waves) it spilled 30 registers to scratch, which
+// moved about 9 GB per launch through HBM for the 256-problem batch (its
+// histogram launches took 22 ms per run against 18 ms without the spills).
 template <class P, int DMAX>
 struct BatchMinWaves {
-    static constexpr int value = (!P::is64 && DMAX == 16) ? 6 : 4;
+    static constexpr int value = 4;
 };
 
 template <class P, int KIND, int DMAX, bool HIST>

@@ -39,8 +39,20 @@ struct MinWaves {
     static constexpr int value = (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 8 : 4;
 };
 
+// Most waves per SIMD the kernel is compiled for.  Beyond d = 8 the kernels
+// with histograms run one 1024-thread block per CU (their LDS holds one
+// block's table and replicated histogram), i.e. 4 waves per SIMD, which the
+// compiler cannot know from the dynamic LDS size: told so, it may use up to
+// 128 registers and keep an event's table reads in flight together instead
+// of waiting on each (the d = 20 bimodal kernel waited on every one).
+template <int DMAX, int HM>
+struct MaxWaves {
+    static constexpr int value = (DMAX > 8 && HM != 0) ? 4 : 8;
+};
+
 template <class P, int KIND, int DMAX, bool EXACT, int HM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<P, KIND, DMAX>::value, 8))) void k_sample(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<P, KIND, DMAX>::value,
+                                                                         MaxWaves<DMAX, HM>::value))) void k_sample(
     SampleArgs a)
 {
     constexpr bool FIX = HM == kHistFixed;

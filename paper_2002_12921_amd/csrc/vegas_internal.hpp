@@ -236,6 +236,7 @@ struct MergeArgs {
     double M;                // events of the iteration (at END)
     const double* gpart;     // MERGE_GRAD: [rows][d + 1] gradient rows of the event kernel
     double* grad_out;        // MERGE_GRAD: [d + 1] (1/M) sum of the rows
+    double* last_out;        // at END, when not null: (I_t, sigma_t) of the iteration
     int rows;
     int rstride;             // doubles per partial row: 2, or pstride when the rows hold H
     int d, N, pstride, kind;

@@ -145,6 +145,16 @@ class Vegas:
         check(lib().vegas_iterate_grad(self._ctx, int(n_events), flags, ctypes.c_void_p(G.data_ptr()), self._s()),
               "iterate_grad")
 
+    def forward_grad(self, params: torch.Tensor, n_events: int, G: torch.Tensor, out: torch.Tensor):
+        """New parameters, then one frozen-grid iteration (no histograms, not
+        recorded or combined) that writes the gradient of its estimate into G
+        (FP64, d + 1) and (I_t, sigma_t) into out (FP64, 2): one library call."""
+        check(lib().vegas_forward_grad(self._ctx, ctypes.c_void_p(params.data_ptr()), params.numel(),
+                                       1 if params.dtype == torch.float32 else 0, int(n_events),
+                                       _lib.ITER_FULL | _lib.NO_HIST | _lib.NO_COMBINE | _lib.NO_RECORD,
+                                       ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(out.data_ptr()), self._s()),
+              "forward_grad")
+
     def refine(self):
         check(lib().vegas_refine(self._ctx, self._s()), "refine")
 

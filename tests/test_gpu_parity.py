@@ -691,6 +691,18 @@ def test_fused_gradient_matches_oracle(prec, d):
     assert abs(s1v - o1) <= tol * o1
     Go, Gabs = oracle.adjoint(oracle.Problem(d, N, oracle.GAUSS, params), E, t, M)
     assert np.all(np.abs(G.cpu().numpy() - Go / M) <= tol * Gabs / M)
+    # the one-call forward (parameters + the same iteration, (I_t, sigma_t)
+    # written by the reduction) on a third context at the same iteration index
+    u = Vegas(d, N, "gauss", [0.5] + [0.5] * d, prec)
+    u.set_edges(E)
+    G2 = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
+    out2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    u.forward_grad(torch.tensor(params, dtype=torch.float64, device="cuda"), M, G2, out2)
+    assert torch.equal(G2, G)
+    I2, sig2 = out2.cpu().numpy()
+    assert I2 == s1v / M
+    assert np.isclose(sig2, np.sqrt(oracle.iteration_stats(s1v, s2v, M)[1]), rtol=1e-12)
+    assert u.result(allow_nonfinite=True)["n_iter"] == 0  # not recorded
     # backward: gout times G, rounded once
     gout = torch.full((1,), 0.75, dtype=torch.float64, device="cuda")
     g32 = torch.zeros(d + 1, dtype=torch.float32, device="cuda")
