@@ -472,9 +472,8 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
             for (int l2 = 4; l2 >= 0; --l2) {
                 if (force_reps && (1 << l2) != force_reps) continue;
                 const size_t lds = lds_for(1 << l2);
-                // 256: the kernel's static LDS (work item, wave partials), and
-                // the discontinuous integrand's thresholds
-                if (lds + 256 + (b->kind == VEGAS_GENZ_DISC ? sizeof(uint64_t) * dm : 0) > kLdsLimit) continue;
+                // 256: the kernel's static LDS (work item, wave partials)
+                if (lds + 256 > kLdsLimit) continue;
                 const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th);
                 cand.push_back(Shape{th, l2, lds, std::max(1, cus * bpc), bpc});
             }
@@ -631,6 +630,7 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
 vegas_status vegas_batch_run(vegas_batch* b, vegas_stream_t stream)
 {
     if (!b) return fail(VEGAS_EINVAL, "batch is NULL");
+    Range r("vegas_batch_run");
     VEGAS_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
     b->next_step = 0;
     return VEGAS_OK;
@@ -642,6 +642,7 @@ vegas_status vegas_batch_step(vegas_batch* b, int32_t k, vegas_stream_t stream)
     if (k < 0 || k >= b->n_iter) return fail(VEGAS_EINVAL, "iteration %d out of [0, %d)", k, b->n_iter);
     if (k != 0 && k != b->next_step)
         return fail(VEGAS_ESTATE, "iteration %d next: steps run in order from 0 (asked for %d)", b->next_step, k);
+    Range r("vegas_batch_step");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (k == 0) VEGAS_HIP(launch_batch_reset(b->args(), b->dmax, b->n_iter, b->kind, s));
     vegas_status st = enqueue_iteration(b, k, s);

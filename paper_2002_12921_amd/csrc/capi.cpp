@@ -555,12 +555,14 @@ extern "C" {
 
 vegas_status vegas_iterate(vegas_ctx* c, int64_t n, uint32_t flags, vegas_stream_t stream)
 {
+    Range r("vegas_iterate");
     return iterate_impl(c, n, flags, nullptr, nullptr, stream);
 }
 
 vegas_status vegas_iterate_grad(vegas_ctx* c, int64_t n, uint32_t flags, double* dev_G, vegas_stream_t stream)
 {
     if (!dev_G) return fail(VEGAS_EINVAL, "dev_G is NULL");
+    Range r("vegas_iterate_grad");
     return iterate_impl(c, n, flags, dev_G, nullptr, stream);
 }
 
@@ -568,6 +570,7 @@ vegas_status vegas_forward_grad(vegas_ctx* c, const void* dev_params, int32_t n_
                                 int64_t n, uint32_t flags, double* dev_G, double* dev_out2, vegas_stream_t stream)
 {
     if (!c || !dev_params || !dev_G || !dev_out2) return fail(VEGAS_EINVAL, "NULL argument");
+    Range r("vegas_forward_grad");
     if (c->kind != VEGAS_GAUSS) return fail(VEGAS_EUNSUPPORTED, "the gradient is implemented for the Gaussian integrand");
     if (n_params != expected_params(c->kind, c->d)) return fail(VEGAS_EINVAL, "expected %d params, got %d",
                                                                expected_params(c->kind, c->d), n_params);
@@ -628,6 +631,7 @@ vegas_status vegas_refine(vegas_ctx* c, vegas_stream_t stream)
     if (!c) return fail(VEGAS_EINVAL, "ctx is NULL");
     if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
     if (!c->has_hist) return fail(VEGAS_ESTATE, "no completed iteration whose histograms are unused");
+    Range r("vegas_refine");
     VEGAS_HIP(launch_refine(merge_args(c, 1, 0, 0.0), static_cast<hipStream_t>(stream)));
     c->has_hist = false;
     c->grid_version += 1;
@@ -637,6 +641,7 @@ vegas_status vegas_refine(vegas_ctx* c, vegas_stream_t stream)
 vegas_status vegas_result(vegas_ctx* c, vegas_result_t* out, vegas_stream_t stream)
 {
     if (!c || !out) return fail(VEGAS_EINVAL, "NULL argument");
+    Range r("vegas_result");
     DevResult R;
     hipStream_t s = static_cast<hipStream_t>(stream);
     VEGAS_HIP(launch_combine(c->P.records, c->P.rec_flag, c->rec_idx, c->P.result, s));
@@ -713,6 +718,7 @@ vegas_status vegas_adjoint(vegas_ctx* c, int64_t iteration, int64_t n, const dou
     if (iteration < 0 || iteration >= (int64_t(1) << 32)) return fail(VEGAS_EINVAL, "iteration out of range");
     if (n < 1 || n > (int64_t(1) << 40)) return fail(VEGAS_EINVAL, "n_events must be in [1, 2^40]");
     if (c->in_chunk) return fail(VEGAS_ESTATE, "an iteration is open");
+    Range r("vegas_adjoint");
     AdjointArgs a{};
     a.cst = c->P.cst;
     a.tab = c->prec == FP64 ? static_cast<const void*>(c->P.tab64) : static_cast<const void*>(c->P.tab32);

@@ -3,6 +3,8 @@
 
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "vegas.h"
 
 namespace vegas {
@@ -25,6 +27,16 @@ constexpr int kStaticDevices = 16;
 // over the static device workspace ws (ws_bytes); allocates nothing.
 vegas_status init_static_ctx(vegas_ctx** out, const vegas_desc* desc, int device, void* ws, size_t ws_bytes,
                              vegas_stream_t stream);
+
+// A roctx range around one entry point's launches: rocprofv3 --marker-trace
+// shows each iteration, refinement and batch step as a named range.  Without
+// a profiler attached a push or pop is a call through an empty dispatch table.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 }  // namespace vegas
 

@@ -126,8 +126,17 @@ struct EvalConsts {
     double k2;          // FP32 path: log2(e)/(a S)^2 (GAUSS, BIMODAL), log2(e) (DISC)
     BinConsts bc;
     double C, Cf, Cw;
+    // DISC: x_i > a_i exactly when the event's binning word k_i >= K_i; lane
+    // l holds K_l (l < d), read with v_readlane (which ignores EXEC, so it is
+    // safe in the partial last pass); never: some K_i = 2^32, no event is
+    // inside
+    uint32_t kv;
+    bool never;
 
-    __device__ __forceinline__ void load(const DevConst* __restrict__ c)
+    // thr_g: the d thresholds T_i of the discontinuous integrand in
+    // P = b 2^32 + lo (disc_threshold; other kinds: unused, may be null).
+    // Called by every thread of the wave (it takes a ballot).
+    __device__ __forceinline__ void load(const DevConst* __restrict__ c, const uint64_t* __restrict__ thr_g, int d)
     {
         // only what the kernel's precision and integrand read (scalar registers
         // are scarce); the FP32 path works on u S, S = 2^(ws + 32), so its
@@ -162,6 +171,20 @@ struct EvalConsts {
         C = c->C;
         Cf = c->Cf;
         Cw = c->Cw;
+        kv = 0;
+        never = false;
+        if constexpr (KIND == GENZ_DISC) {
+            // P = k N + floor(N/2) grows with k, so P >= T exactly when
+            // k >= K = ceil((T - floor(N/2)) / N) (0 when T <= floor(N/2))
+            const int lane = int(threadIdx.x & 63u);
+            uint64_t K = 0;
+            if (lane < d) {
+                const uint64_t T = thr_g[lane], off = N >> 1;
+                K = T <= off ? 0 : (T - off + N - 1) / N;
+            }
+            never = __ballot(K > 0xffffffffull) != 0;
+            kv = uint32_t(K);
+        }
     }
 };
 
@@ -186,7 +209,7 @@ struct EventEval {
     int fe;           // FP32: binary exponent of the integrand (f ~ 2^fe F)
 
     __device__ __forceinline__ void run(const EvalConsts<P, KIND, DMAX>& c, const tab_t* __restrict__ tab,
-                                        const uint64_t* __restrict__ thr, uint64_t e, uint32_t t,
+                                        uint64_t e, uint32_t t,
                                         uint32_t ctr3, uint32_t key0, uint32_t key1, int d_rt, int N)
     {
         // every fused multiply-add here is an explicit fma(): nothing else is
@@ -265,10 +288,9 @@ struct EventEval {
                             }
                         } else if constexpr (KIND == GENZ_DISC) {
                             // x_i > a_i as the FP64 x decides it: one integer
-                            // comparison of b 2^32 + lo with the dimension's
-                            // threshold (disc_threshold), in both precisions
-                            const uint64_t Pw = (uint64_t(uint32_t(bi)) << 32) | lo;
-                            inside = inside && (Pw >= thr[i]);
+                            // comparison of the binning word with K_i, in both
+                            // precisions
+                            inside = inside & (k.w[q] >= uint32_t(__builtin_amdgcn_readlane(int(c.kv), i)));
                             if constexpr (P::is64)
                                 sa = fma(c.p1[i], ui, sa);
                             else if constexpr (kQ32)
@@ -295,6 +317,7 @@ struct EventEval {
                 }
             }
         }
+        if constexpr (KIND == GENZ_DISC) inside = inside && !c.never;
         wp = w;
         s = sa;
         s64 = P::is64 ? double(sa) : double(qa);

@@ -31,7 +31,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
     extern __shared__ __align__(128) unsigned char smem[];
     __shared__ int s_item;
     __shared__ double red[kBlock / 64];
-    __shared__ uint64_t thr[KIND == GENZ_DISC ? DMAX : 1];  // x_i > a_i thresholds of the problem
     // histogram [dim][bin][replica], lane l adding into replica l mod rep
     const int rl2 = a.hrep_log2, rep = 1 << rl2;
     const int lrep = int(threadIdx.x) & (rep - 1);
@@ -56,12 +55,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
             key0 = pr.key0;
             key1 = pr.key1;
             ctr3 = pr.ctr3;
-            cst.load(pr.cst);
+            cst.load(pr.cst, pr.thr, d);
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
             for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
-            if constexpr (KIND == GENZ_DISC)
-                for (int k = threadIdx.x; k < d; k += blockDim.x) thr[k] = pr.thr[k];
             hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
         }
         if constexpr (HIST)
@@ -72,7 +69,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         int ng = 0;
         for (uint64_t k = threadIdx.x; k < it.n; k += blockDim.x) {
             EventEval<P, KIND, DMAX> ev;
-            ev.run(cst, tab, thr, it.e0 + k, a.t, ctr3, key0, key1, d, N);
+            ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
             double v, v2;
             {
                 // rounded as written in every variant (with or without histograms)

@@ -71,15 +71,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
     tab_t* tab = reinterpret_cast<tab_t*>(smem + (FIX ? hist_bytes : 0));
     double* hist = reinterpret_cast<double*>(smem + (FIX ? 0 : tab_bytes));
     double* red = reinterpret_cast<double*>(smem + tab_bytes + hist_bytes);
-    // the discontinuous integrand's thresholds follow the wave partials
-    uint64_t* thr = reinterpret_cast<uint64_t*>(smem + tab_bytes + hist_bytes + sizeof(double) * (kBlock / 64));
     // the lane's replica within the bin: byte offset lrep * 8 (fixed layout)
     unsigned char* hlane = smem + (lrep << 3);
 
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
     for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
-    if constexpr (KIND == GENZ_DISC)
-        for (int k = threadIdx.x; k < a.d; k += blockDim.x) thr[k] = a.thr[k];
     {   // clear the histogram, 16 bytes per store (hist is 128-byte aligned), then an odd last double
         double2* h2 = reinterpret_cast<double2*>(hist);
         for (int k = threadIdx.x; k < int(hist_bytes / sizeof(double2)); k += blockDim.x)
@@ -89,7 +85,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
     __syncthreads();
 
     EvalConsts<P, KIND, DMAX> cst;
-    cst.load(a.cst);
+    cst.load(a.cst, a.thr, a.d);
     const int d = EXACT ? DMAX : a.d;
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
     double g1 = 0.0, g2 = 0.0;
@@ -99,7 +95,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t k = uint64_t(threadIdx.x) * gridDim.x + blockIdx.x; k < a.n; k += stride) {
         EventEval<P, KIND, DMAX, EXACT> ev;
-        ev.run(cst, tab, thr, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
+        ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
         double v, v2;
         {
             // rounded as written in every variant (with or without histograms)
@@ -179,18 +175,15 @@ __global__ __launch_bounds__(kBlock) void k_dump(DumpArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     const int dN = a.d * a.N;
     tab_t* tab = reinterpret_cast<tab_t*>(smem);
-    uint64_t* thr = reinterpret_cast<uint64_t*>(smem + ((size_t(dN) * sizeof(tab_t) + 15) & ~size_t(15)));
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
-    for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
-    if constexpr (KIND == GENZ_DISC)
-        for (int k = threadIdx.x; k < a.d; k += kBlock) thr[k] = a.thr[k];
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
     __syncthreads();
     EvalConsts<P, KIND, DMAX> cst;
-    cst.load(a.cst);
+    cst.load(a.cst, a.thr, a.d);
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
         EventEval<P, KIND, DMAX> ev;
-        ev.run(cst, tab, thr, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
+        ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, a.d, a.N);
         double* row = a.out + k * size_t(3 * a.d + 2);
         // x = centre + u; delta as the kernel represents it (FP32: (RN32(lo) +
         // h)/2^32, and u carries the factor S); w and f with their exponents
@@ -225,12 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     tab_t* tab = reinterpret_cast<tab_t*>(smem);
     double* red = reinterpret_cast<double*>(smem + tab_bytes);
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
-    for (int k = threadIdx.x; k < dN; k += kBlock) tab[k] = gtab[k];
+    for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
     __syncthreads();
 
     const DevConst* c = a.cst;
     EvalConsts<P, GAUSS, DMAX> cst;
-    cst.load(c);
+    cst.load(c, nullptr, a.d);
     // the FP32 path's u carries the factor S = 2^(ws + 32): its constants take S^-1, S^-2 (exact)
     const double ds = P::is64 ? 1.0 : double(c->dscale32) * 0x1p-32;
     const real ka = P::is64 ? real(c->kexp64) : real(double(c->ka32) * ds);
@@ -246,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < a.n; k += stride) {
         EventEval<P, GAUSS, DMAX, EXACT> ev;
-        ev.run(cst, tab, nullptr, k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
+        ev.run(cst, tab, k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
         const double v = ev.value(cst);
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
@@ -297,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_grad(SampleArgs a, double* gp
 
     const DevConst* c = a.cst;
     EvalConsts<P, GAUSS, DMAX> cst;
-    cst.load(c);
+    cst.load(c, nullptr, a.d);
     const double ds = P::is64 ? 1.0 : double(c->dscale32) * 0x1p-32;
     const real ka = P::is64 ? real(c->kexp64) : real(double(c->ka32) * ds);
     const real ka2 = real(2) * ka;
@@ -313,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_grad(SampleArgs a, double* gp
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t k = uint64_t(threadIdx.x) * gridDim.x + blockIdx.x; k < a.n; k += stride) {
         EventEval<P, GAUSS, DMAX, EXACT> ev;
-        ev.run(cst, tab, nullptr, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
+        ev.run(cst, tab, a.e0 + k, a.t, a.ctr3, a.key0, a.key1, d, a.N);
         double v, v2;
         {
 #pragma clang fp contract(off)
@@ -476,8 +469,8 @@ hipError_t launch_sample_grad(int prec, const SampleArgs& a, double* gpart, int 
 
 size_t sample_lds(int prec, int kind, int d, int N, int rep, bool hist)
 {
-    // wave partials, then (discontinuous integrand) the d thresholds
-    const size_t red = sizeof(double) * (kBlock / 64) + (kind == GENZ_DISC ? sizeof(uint64_t) * d : 0);
+    // the wave partials of the block sums follow the table and histogram
+    const size_t red = sizeof(double) * (kBlock / 64);
     switch (hist_mode(d, N, rep, hist)) {
     case kHistNone: return lds_bytes(prec, kind, d, N, 0) + red;
     case kHistFixed: return size_t(d) * kFixDimBytes + lds_bytes(prec, kind, d, N, 0) + red;
@@ -498,7 +491,7 @@ hipError_t launch_dump(int prec, int kind, const DumpArgs& a, hipStream_t s)
 {
     const void* fn = prec == FP64 ? dump_fn_kind<P64>(kind, a.d) : dump_fn_kind<P32>(kind, a.d);
     const size_t tab = size_t(a.d) * a.N * tab_entry_bytes(prec, kind);
-    const size_t lds = ((tab + 15) & ~size_t(15)) + (kind == GENZ_DISC ? sizeof(uint64_t) * a.d : 0);
+    const size_t lds = tab;
     uint64_t blocks = (a.n + kBlock - 1) / kBlock;
     if (blocks > 1024) blocks = 1024;
     if (blocks == 0) blocks = 1;

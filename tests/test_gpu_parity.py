@@ -164,6 +164,44 @@ def test_genz_disc_decision_at_the_threshold(prec, N):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("N", [40, 7])
+def test_genz_disc_extreme_thresholds(prec, N):
+    """The ends of the x_i > a_i decision: a_i = 0, where every event is
+    inside (the event's word k need only be >= 0), and a_i the largest double
+    below 1 in one dimension, where no event is (the bin's threshold lies past
+    its last event, so the integrand is zero everywhere and so are the sums);
+    decisions and sums against the oracle's, on the uniform and on an adapted
+    grid."""
+    d, M, t = 5, 20_000, 2
+    c = list(np.linspace(1.0, 2.0, d))
+    kid = oracle.GENZ_DISC
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    E_ad = _adapted_edges(d, N, c + [0.3] * d, kind=kid, iters=2, n=20_000)
+    for E in (oracle.uniform_edges(d, N), E_ad):
+        for case in ("all", "none"):
+            a = [0.0] * d
+            if case == "none":
+                a[2] = float(np.nextafter(1.0, 0.0))
+            params = c + a
+            pr = oracle.Problem(d, N, kid, params, seed=5)
+            v = Vegas(d, N, "genz_disc", params, prec, seed=5)
+            v.set_edges(E)
+            got = v.dump_events(0, M, iteration=t).cpu().numpy()
+            ref = oracle.events(pr, E, t, 0, M)
+            inside_ref = ref[:, 3 * d + 1] != 0.0
+            assert inside_ref.all() if case == "all" else not inside_ref.any()
+            assert np.array_equal(got[:, 3 * d + 1] != 0.0, inside_ref), (prec, N, case)
+            v.iterate(M)
+            S1, S2, H = v.last_iteration()
+            o1, o2, Ho = oracle.accumulate(pr, E, 0, M)
+            if case == "none":
+                assert S1 == 0.0 and S2 == 0.0 and o1 == 0.0 and not np.any(H)
+            else:
+                assert abs(S1 - o1) <= tol * abs(o1) and abs(S2 - o2) <= tol * abs(o2)
+                assert _hist_close(H, Ho, tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
 def test_event_index_beyond_2_32(prec):
     """Events whose index needs the counter's second word (e >= 2^32): event
     records straddling 2^32 against the oracle's, one by one, and an
