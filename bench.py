@@ -98,6 +98,21 @@ def measured_counters():
         f"{os.path.relpath(PMC_SUMMARY, ROOT)}")
 
 
+_CLOCK_CTX = []
+
+
+def warm_clock():
+    """About 0.1 s of back-to-back d = 8 event-kernel launches, untimed (the
+    context's state stays as it was): the GPU's clock drops within half a
+    second of idling and needs tens of ms of load to come back, so every
+    timed leg starts after this burst, whatever its own warm-up."""
+    from paper_2002_12921_amd import Vegas
+
+    if not _CLOCK_CTX:
+        _CLOCK_CTX.append(Vegas(D, NBINS, "gauss", [A] + [0.5] * D, "fp32_mixed", seed=0, alpha=ALPHA))
+    _CLOCK_CTX[0].time_event_kernel(EVENTS, CLOCK_WARM_LAUNCHES)
+
+
 def _events_per_s(ms_per_step: float) -> float:
     return EVENTS / (ms_per_step * 1e-3)
 
@@ -112,6 +127,7 @@ def time_accumulation(precision: str, steps: int, warmup: int, adapt: int = 5):
     v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
     for _ in range(adapt):
         v.iterate(EVENTS, refine=True, combine=False)
+    warm_clock()
     for _ in range(warmup):
         v.iterate(EVENTS, hist=False)
     v.reset_results()
@@ -207,6 +223,7 @@ def c2_schedule(precision: str):
     from paper_2002_12921_amd import Vegas
 
     v = Vegas(D, NBINS, "gauss", [A] + [0.5] * D, precision, seed=0, alpha=ALPHA)
+    warm_clock()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(5):
@@ -246,6 +263,7 @@ def c2_schedule_graph(precision: str, integral: float, sigma: float, reps: int =
         for _ in range(5):
             v.iterate(EVENTS, hist=False)
     ms, worst = [], 0.0
+    warm_clock()
     for _ in range(reps):
         v.set_edges(E0)  # on s, before the replay
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -278,6 +296,7 @@ def batch_c5(reps: int):
     b = VegasBatch(probs, n_iter, n_adapt)
     plan_s = time.perf_counter() - t0
     b.run()
+    warm_clock()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
@@ -292,6 +311,7 @@ def batch_c5(reps: int):
 
     ctxs = [Vegas(q["dim"], q["n_bins"], "gauss", q["params"], q["precision"], seed=q["seed"],
                   alpha=q["alpha"], problem=q["problem"]) for q in probs]
+    warm_clock()
     torch.cuda.synchronize()
     start.record()
     for v, q in zip(ctxs, probs):
@@ -325,6 +345,7 @@ def c3_streamed():
             v.iterate(per, chunk=ch, refine=adapt, combine=not adapt, hist=adapt)
 
     iteration(True)  # warm-up (its own grid step)
+    warm_clock()
     v.reset_results()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -362,7 +383,8 @@ def differentiable_c4(steps: int, warmup: int):
         a.grad = None
         vegas_integral(mu, a, v, EVENTS).backward()
 
-    for _ in range(max(2, warmup)):  # the clock ramps up over tens of ms of load
+    warm_clock()
+    for _ in range(max(2, warmup)):
         step()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -388,6 +410,7 @@ def genz_d16(steps: int, warmup: int):
     for kind in ("genz_disc", "genz_peak"):
         for prec in ("fp32_mixed", "fp64"):
             v = Vegas(16, NBINS, kind, workloads.genz16(kind), prec, seed=0, alpha=ALPHA)
+            warm_clock()
             for _ in range(warmup):
                 v.iterate(EVENTS, refine=True, combine=False)
             v.reset_results()
@@ -419,6 +442,7 @@ def c1_small(reps: int):
 
     def run():
         v = Vegas(d, NBINS, "gauss", params, "fp64", seed=0, alpha=ALPHA)
+        warm_clock()
         torch.cuda.synchronize()
         start.record()
         for _ in range(n_iter):

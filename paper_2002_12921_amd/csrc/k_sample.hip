@@ -274,8 +274,18 @@ __global__ __launch_bounds__(kMergeThreads) void k_adjoint_merge(AdjointArgs a, 
 // grouped Kahan S1, S2, so the estimate is bitwise that of k_sample -- that
 // also sums each event's v d ln f / d theta_j, as k_adjoint does, into
 // per-block rows gpart[block][d + 1] (merged by k_merge's gradient block).
+// It launches like the event kernel (two 1024-thread blocks per CU, 8 waves
+// per SIMD), so FP32 with d = 4 or 8 is compiled for 8 waves: at its natural
+// 70 registers (d = 8) only one block fitted per CU and the grid ran in two
+// rounds of 4 waves per SIMD.
 template <class P, int DMAX, bool EXACT>
-__global__ __launch_bounds__(kBlock) void k_sample_grad(SampleArgs a, double* gpart)
+struct GradMinWaves {
+    static constexpr int value = (!P::is64 && DMAX <= 8 && EXACT) ? 8 : 1;
+};
+
+template <class P, int DMAX, bool EXACT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GradMinWaves<P, DMAX, EXACT>::value))) void
+k_sample_grad(SampleArgs a, double* gpart)
 {
     using tab_t = typename TabEntry<P, GAUSS>::type;
     using real = typename P::real;
