@@ -323,8 +323,8 @@ vegas_status vegas_set_launch(vegas_ctx* ctx, int32_t n_blocks);
  * FP64 rounding. */
 vegas_status vegas_set_hist_replicas(vegas_ctx* ctx, int32_t replicas);
 /* The automatic choice: blocks (compute units x resident blocks per unit),
- * resident blocks per compute unit, threads per block (1024, 512 or 256,
- * whichever keeps the most waves resident) and histogram replicas in use.
+ * resident blocks per compute unit, threads per block (1024, 768, 512 or
+ * 256, whichever keeps the most waves resident) and histogram replicas in use.
  * Any pointer may be NULL. */
 vegas_status vegas_get_launch(const vegas_ctx* ctx, int32_t* auto_blocks, int32_t* blocks_per_cu,
                               int32_t* threads, int32_t* replicas);

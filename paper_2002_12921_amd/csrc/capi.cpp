@@ -379,7 +379,10 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
     const double* kRepFactor = c->d > 8 ? kRepFactorHigh : kRepFactorLow;
     double best = -1.0;
     int per_cu = 1;
-    for (int th : {1024, 512, 256}) {
+    // 768 comes after 512, so it is taken only where it holds strictly more
+    // waves (two blocks per CU where the LDS admits two and the registers
+    // allow 6 or 7 waves per SIMD: the FP64 kernels up to d = 8)
+    for (int th : {1024, 512, 768, 256}) {
         if (source && th > kUserThreads) continue;
         for (int l2 = 4; l2 >= 0; --l2) {
             const size_t lds = event_lds(c, 1 << l2, true);

@@ -28,15 +28,18 @@ constexpr int kFixBins = 64;
 constexpr int kFixRepLog2 = 4;
 constexpr int kFixDimBytes = kFixBins << (kFixRepLog2 + 3);
 
-// Fewest waves per SIMD the register allocation must allow.  8 (64 VGPRs, two
-// 1024-thread blocks per CU) for the FP64 Gaussian, bimodal and product-peak
-// kernels up to d = 8: they then spill a few registers but issue from more
-// waves (d = 8 Gaussian: 64.2 against 67.2 us per 1e7 events).  4 elsewhere:
+// Fewest waves per SIMD the register allocation must allow.  6 (80 VGPRs) for
+// the FP64 Gaussian, bimodal and product-peak kernels up to d = 8: they then
+// fit without spills, and the launch runs two 768-thread blocks per CU (the
+// fixed histogram layout's LDS admits two blocks), 6 waves per SIMD.  At 8
+// waves (64 VGPRs, two 1024-thread blocks) the d = 8 Gaussian spilled 15
+// registers and took 62.2-63.0 us per 1e7 events, at 7 (896-thread blocks)
+// it still spilled 8 and took 70.0-70.8 us, at 6: 57.9-58.5 us.  4 elsewhere:
 // the discontinuous integrand and larger d would spill heavily, and the
 // FP32-mixed kernels reach 8 waves by themselves.
 template <class P, int KIND, int DMAX>
 struct MinWaves {
-    static constexpr int value = (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 8 : 4;
+    static constexpr int value = (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 6 : 4;
 };
 
 // Most waves per SIMD the kernel is compiled for.  Beyond d = 8 the kernels
