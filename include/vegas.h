@@ -221,9 +221,14 @@ vegas_status vegas_iterate_grad(vegas_ctx* ctx, int64_t n_events, uint32_t flags
  * training loops, where every host call costs): vegas_set_params_device
  * (dev_params, n_params, is_fp32), then vegas_iterate_grad(n_events, flags,
  * dev_G), whose reduction also writes (I_t, sigma_t) of the iteration to
- * dev_out2[2] (device FP64).  Gaussian integrand; flags as for
- * vegas_iterate_grad.  Arguments are checked before anything is launched. */
-vegas_status vegas_forward_grad(vegas_ctx* ctx, const void* dev_params, int32_t n_params, int32_t is_fp32,
+ * dev_out2[2] (device FP64).  dev_params_rest: NULL (all n_params values in
+ * dev_params), or the values 1..n_params-1, with only value 0 in dev_params
+ * (the Gaussian's a, with mu[0..d-1] in dev_params_rest: separate a and mu
+ * arrays need no concatenation); both in the same type.  Gaussian
+ * integrand; flags as for vegas_iterate_grad.  Arguments are checked before
+ * anything is launched. */
+vegas_status vegas_forward_grad(vegas_ctx* ctx, const void* dev_params, const void* dev_params_rest,
+                                int32_t n_params, int32_t is_fp32,
                                 int64_t n_events, uint32_t flags, double* dev_G, double* dev_out2,
                                 vegas_stream_t stream);
 

@@ -88,7 +88,7 @@ def lib() -> ctypes.CDLL:
         "vegas_user_compile": [ctypes.c_char_p, i32, i32, ctypes.c_char_p, sz],
         "vegas_iterate": [vp, i64, u32, vp],
         "vegas_iterate_grad": [vp, i64, u32, vp, vp],
-        "vegas_forward_grad": [vp, vp, i32, i32, i64, u32, vp, vp, vp],
+        "vegas_forward_grad": [vp, vp, vp, i32, i32, i64, u32, vp, vp, vp],
         "vegas_grad_scale": [vp, vp, vp, i32, i32, vp],
         "vegas_refine": [vp, vp],
         "vegas_result": [vp, P(Result), vp],

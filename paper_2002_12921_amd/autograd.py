@@ -36,17 +36,23 @@ class VegasIntegral(torch.autograd.Function):
         # parameter layout of the Gaussian integrand: a, mu[0..d-1]; FP32
         # parameters go to the library as they are (it widens them, exactly)
         pt = torch.float32 if mu.dtype == torch.float32 and a.dtype == torch.float32 else torch.float64
-        params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
-        out = torch.empty(2, dtype=torch.float64, device=mu.device)
         ctx.G = None
         if fused:
             # one library call: the parameters, then the frozen-grid iteration
             # (no histograms, no record slot) whose launch also sums the
-            # gradient terms, its (I_t, sigma_t) written to out
-            G = torch.empty(d + 1, dtype=torch.float64, device=mu.device)
-            vegas.forward_grad(params, n_events, G, out)
+            # gradient terms, its (I_t, sigma_t) written to out; a and mu go
+            # as two arrays when they already have the type (no concatenation)
+            buf = torch.empty(d + 3, dtype=torch.float64, device=mu.device)
+            G, out = buf[:d + 1], buf[d + 1:]
+            if a.dtype == pt and mu.dtype == pt and mu.is_contiguous():
+                vegas.forward_grad(a.detach(), n_events, G, out, rest=mu.detach())
+            else:
+                params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
+                vegas.forward_grad(params, n_events, G, out)
             ctx.G = G
         else:
+            params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
+            out = torch.empty(2, dtype=torch.float64, device=mu.device)
             vegas.set_params_device(params)
             ctx.t = vegas.iteration_index
             # frozen grid: no histograms (the sums are bitwise those of the

@@ -569,8 +569,9 @@ vegas_status vegas_iterate_grad(vegas_ctx* c, int64_t n, uint32_t flags, double*
     return iterate_impl(c, n, flags, dev_G, nullptr, stream);
 }
 
-vegas_status vegas_forward_grad(vegas_ctx* c, const void* dev_params, int32_t n_params, int32_t is_fp32,
-                                int64_t n, uint32_t flags, double* dev_G, double* dev_out2, vegas_stream_t stream)
+vegas_status vegas_forward_grad(vegas_ctx* c, const void* dev_params, const void* dev_params_rest, int32_t n_params,
+                                int32_t is_fp32, int64_t n, uint32_t flags, double* dev_G, double* dev_out2,
+                                vegas_stream_t stream)
 {
     if (!c || !dev_params || !dev_G || !dev_out2) return fail(VEGAS_EINVAL, "NULL argument");
     Range r("vegas_forward_grad");
@@ -587,7 +588,7 @@ vegas_status vegas_forward_grad(vegas_ctx* c, const void* dev_params, int32_t n_
         return fail(VEGAS_ESTATE, "%d iterations recorded: call vegas_reset_results", kMaxRecords);
     if (c->t >= (int64_t(1) << 32)) return fail(VEGAS_ESTATE, "iteration index exhausted");
     VEGAS_HIP(launch_set_params(c->prec, c->kind, c->d, c->N, dev_params, n_params, is_fp32 ? 1 : 0, c->P,
-                                static_cast<hipStream_t>(stream)));
+                                static_cast<hipStream_t>(stream), dev_params_rest));
     c->params_version += 1;
     return iterate_impl(c, n, flags, dev_G, dev_out2, stream);
 }

@@ -122,11 +122,15 @@ __global__ void k_prepare(int prec, int kind, int d, int N, const double* __rest
 // the centres taken from the parameters themselves, so no block waits for
 // another.
 __global__ __launch_bounds__(256) void k_set_params(int prec, int kind, int d, int N, const void* __restrict__ src,
-                                                    int n, int is_fp32, ProblemPtrs p)
+                                                    const void* __restrict__ rest, int n, int is_fp32, ProblemPtrs p)
 {
     __shared__ double q[kMaxParams];
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        q[k] = is_fp32 ? double(static_cast<const float*>(src)[k]) : static_cast<const double*>(src)[k];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        // value k: src[k], or with rest given, src[0] and rest[k - 1]
+        const void* a = rest && k > 0 ? rest : src;
+        const int j = rest && k > 0 ? k - 1 : k;
+        q[k] = is_fp32 ? double(static_cast<const float*>(a)[j]) : static_cast<const double*>(a)[j];
+    }
     __syncthreads();
     const int i = blockIdx.x;
     if (i == 0) {
@@ -255,9 +259,9 @@ hipError_t launch_combine(const double* records, const int32_t* rec_flag, int n_
 }
 
 hipError_t launch_set_params(int prec, int kind, int d, int N, const void* src, int n, int is_fp32,
-                             const ProblemPtrs& p, hipStream_t s)
+                             const ProblemPtrs& p, hipStream_t s, const void* rest)
 {
-    hipLaunchKernelGGL(k_set_params, dim3(d), dim3(256), 0, s, prec, kind, d, N, src, n, is_fp32, p);
+    hipLaunchKernelGGL(k_set_params, dim3(d), dim3(256), 0, s, prec, kind, d, N, src, rest, n, is_fp32, p);
     return hipGetLastError();
 }
 

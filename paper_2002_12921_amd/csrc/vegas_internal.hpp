@@ -310,8 +310,9 @@ hipError_t launch_build_tables(const ProblemPtrs& p, int kind, int d, int N, hip
 hipError_t launch_zero(double* x, size_t n, hipStream_t s);
 hipError_t launch_combine(const double* records, const int32_t* rec_flag, int n_rec, DevResult* result,
                           hipStream_t s);
+// rest: null (all n values in src), or values 1..n-1 (src holds value 0)
 hipError_t launch_set_params(int prec, int kind, int d, int N, const void* src, int n, int is_fp32,
-                             const ProblemPtrs& p, hipStream_t s);
+                             const ProblemPtrs& p, hipStream_t s, const void* rest = nullptr);
 hipError_t launch_reset_results(double* records, int32_t* rec_flag, DevResult* result,
                                 hipStream_t s);
 hipError_t launch_copy_last(const DevResult* result, double* out2, hipStream_t s);

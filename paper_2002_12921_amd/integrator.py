@@ -19,9 +19,17 @@ INTEGRANDS = {"gauss": _lib.GAUSS, "bimodal": _lib.BIMODAL,
 PRECISIONS = {"fp64": _lib.FP64, "fp32_mixed": _lib.FP32_MIXED, "mixed": _lib.FP32_MIXED}
 
 
-def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+# the current stream's handle without building a Stream object (a few
+# microseconds per call otherwise, which a training loop pays on every step)
+_raw_current_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    if stream is not None:
+        return stream.cuda_stream
+    if _raw_current_stream is not None:
+        return _raw_current_stream(torch.cuda.current_device())
+    return torch.cuda.current_stream().cuda_stream
 
 
 def make_desc(dim: int, n_bins: int, integrand, params: Sequence[float], precision="fp64",
@@ -145,14 +153,18 @@ class Vegas:
         check(lib().vegas_iterate_grad(self._ctx, int(n_events), flags, ctypes.c_void_p(G.data_ptr()), self._s()),
               "iterate_grad")
 
-    def forward_grad(self, params: torch.Tensor, n_events: int, G: torch.Tensor, out: torch.Tensor):
+    def forward_grad(self, params: torch.Tensor, n_events: int, G: torch.Tensor, out: torch.Tensor,
+                     rest: Optional[torch.Tensor] = None):
         """New parameters, then one frozen-grid iteration (no histograms, not
         recorded or combined) that writes the gradient of its estimate into G
-        (FP64, d + 1) and (I_t, sigma_t) into out (FP64, 2): one library call."""
-        check(lib().vegas_forward_grad(self._ctx, ctypes.c_void_p(params.data_ptr()), params.numel(),
+        (FP64, d + 1) and (I_t, sigma_t) into out (FP64, 2): one library call.
+        rest: None (all parameters in params), or the parameters after the
+        first, with params holding only the first (a, then mu), same dtype."""
+        n = params.numel() if rest is None else 1 + rest.numel()
+        check(lib().vegas_forward_grad(self._ctx, params.data_ptr(), None if rest is None else rest.data_ptr(), n,
                                        1 if params.dtype == torch.float32 else 0, int(n_events),
                                        _lib.ITER_FULL | _lib.NO_HIST | _lib.NO_COMBINE | _lib.NO_RECORD,
-                                       ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(out.data_ptr()), self._s()),
+                                       G.data_ptr(), out.data_ptr(), self._s()),
               "forward_grad")
 
     def refine(self):
@@ -199,8 +211,7 @@ class Vegas:
         """grad = gout * G (d + 1 values), one rounding to grad's dtype."""
         assert G.is_cuda and G.dtype == torch.float64 and gout.is_cuda and gout.dtype == torch.float64
         assert grad.is_cuda and grad.dtype in (torch.float64, torch.float32) and grad.is_contiguous()
-        check(lib().vegas_grad_scale(ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(gout.data_ptr()),
-                                     ctypes.c_void_p(grad.data_ptr()), self.dim + 1,
+        check(lib().vegas_grad_scale(G.data_ptr(), gout.data_ptr(), grad.data_ptr(), self.dim + 1,
                                      1 if grad.dtype == torch.float32 else 0, self._s()), "grad_scale")
 
     def adjoint(self, iteration: int, n_events: int, gout: torch.Tensor, grad: torch.Tensor):

@@ -737,8 +737,16 @@ def test_fused_gradient_matches_oracle(prec, d):
     u.set_edges(E)
     G2 = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
     out2 = torch.zeros(2, dtype=torch.float64, device="cuda")
-    u.forward_grad(torch.tensor(params, dtype=torch.float64, device="cuda"), M, G2, out2)
+    pt = torch.tensor(params, dtype=torch.float64, device="cuda")
+    u.forward_grad(pt, M, G2, out2)
     assert torch.equal(G2, G)
+    # the same with a and mu as two arrays (value 0, then the rest)
+    u2 = Vegas(d, N, "gauss", [0.5] + [0.5] * d, prec)
+    u2.set_edges(E)
+    G3 = torch.zeros(d + 1, dtype=torch.float64, device="cuda")
+    out3 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    u2.forward_grad(pt[:1].clone(), M, G3, out3, rest=pt[1:].clone())
+    assert torch.equal(G3, G) and torch.equal(out3, out2)
     I2, sig2 = out2.cpu().numpy()
     assert I2 == s1v / M
     assert np.isclose(sig2, np.sqrt(oracle.iteration_stats(s1v, s2v, M)[1]), rtol=1e-12)
