@@ -124,6 +124,13 @@ def test_null_context_calls():
     assert L.vegas_result(None, ctypes.byref(r), None) == _lib.VEGAS_EINVAL
     assert L.vegas_destroy(None) == _lib.VEGAS_OK
     assert L.vegas_batch_destroy(None) == _lib.VEGAS_OK
+    # the differentiable entry points refuse NULL arguments before any HIP call
+    fake = ctypes.c_void_p(4096)
+    assert L.vegas_forward_grad(None, fake, None, 9, 1, 1000, _lib.ITER_FULL | _lib.NO_HIST, fake, fake, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_forward_grad(None, fake, fake, 9, 1, 1000, _lib.ITER_FULL | _lib.NO_HIST, fake, None, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_grad_scale(None, fake, fake, 9, 0, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_grad_scale(fake, fake, fake, 0, 0, None) == _lib.VEGAS_EINVAL
+    assert L.vegas_iterate_grad(None, 1000, _lib.ITER_FULL | _lib.NO_HIST, fake, None) == _lib.VEGAS_EINVAL
 
 
 GOOD_SRC = """
