@@ -17,12 +17,14 @@ namespace vegas {
 // Histogram modes of the event kernel:
 //   kHistNone    no histograms (an iteration whose grid is not refined);
 //   kHistGeneral table first, then the histogram with runtime strides;
-//   kHistFixed   d in {4, 8}, N <= 64, 16 replicas: the histogram starts the
-//                LDS block with a compile-time stride of 64 bins x 16
-//                replicas (8 KiB) per dimension, so an atomic's address is
+//   kHistFixed   d in {4, 8, 12, 16}, N <= 64, 16 replicas: the histogram
+//                starts the LDS block with a compile-time stride of 64 bins x
+//                16 replicas (8 KiB) per dimension, so an atomic's address is
 //                one shift-add of the bin onto the lane's replica offset and
 //                the dimension's offset rides in the instruction's immediate
-//                field; the grid table follows the histogram.
+//                field; the grid table follows the histogram (at d = 16:
+//                128 KiB + the table, one 1024-thread block per CU, as the
+//                general layout's 16 replicas need anyway).
 constexpr int kHistNone = 0, kHistGeneral = 1, kHistFixed = 2;
 constexpr int kFixBins = 64;
 constexpr int kFixRepLog2 = 4;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves
     SampleArgs a)
 {
     constexpr bool FIX = HM == kHistFixed;
-    static_assert(!FIX || (EXACT && DMAX <= 8), "fixed layout: d <= 8 only");
+    static_assert(!FIX || (EXACT && DMAX <= 16), "fixed layout: d <= 16 only");
     using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(128) unsigned char smem[];
     const int dN = a.d * a.N;
@@ -397,7 +399,8 @@ static int dim_bucket(int d)
 static int hist_mode(int d, int N, int rep, bool hist)
 {
     if (!hist) return kHistNone;
-    return (d == 4 || d == 8) && N <= kFixBins && rep == (1 << kFixRepLog2) ? kHistFixed : kHistGeneral;
+    return (d == 4 || d == 8 || d == 12 || d == 16) && N <= kFixBins && rep == (1 << kFixRepLog2) ? kHistFixed
+                                                                                                 : kHistGeneral;
 }
 
 template <class P, int KIND>
@@ -405,7 +408,9 @@ static const void* sample_fn(int d, int hm)
 {
     if (hm == kHistFixed) {
         if (d == 4) return reinterpret_cast<const void*>(&k_sample<P, KIND, 4, true, kHistFixed>);
-        return reinterpret_cast<const void*>(&k_sample<P, KIND, 8, true, kHistFixed>);
+        if (d == 8) return reinterpret_cast<const void*>(&k_sample<P, KIND, 8, true, kHistFixed>);
+        if (d == 12) return reinterpret_cast<const void*>(&k_sample<P, KIND, 12, true, kHistFixed>);
+        return reinterpret_cast<const void*>(&k_sample<P, KIND, 16, true, kHistFixed>);
     }
     if (hm == kHistNone) {
         if (d == dim_bucket(d)) {
