@@ -116,6 +116,7 @@ struct vegas_batch {
         int blocks = 0;
         int threads = kBlock;
         int hrep_log2 = 0;
+        int fix_l2 = 0;         // the histogram launch's fixed layout (log2 of its replicas), 0: general
         double tuned_ms = 0.0;  // its launches' time in one run (n_adapt with, the rest without histograms)
     };
     std::vector<Bucket> buckets;
@@ -222,7 +223,7 @@ vegas_status enqueue_iteration(vegas_batch* b, int k, hipStream_t s, const hipEv
         ab.item_hi = bk.hi;
         ab.hrep_log2 = bk.hrep_log2;
         if (ev) VEGAS_HIP(hipEventRecord(ev[2 * q], s));
-        VEGAS_HIP(launch_batch_sample(b->prec, b->kind, bk.dmax, bk.lds, ab, bk.blocks, bk.threads, adapt, s));
+        VEGAS_HIP(launch_batch_sample(b->prec, b->kind, bk.dmax, bk.lds, ab, bk.blocks, bk.threads, adapt, bk.fix_l2, s));
         if (ev) VEGAS_HIP(hipEventRecord(ev[2 * q + 1], s));
     }
     const int flags = adapt ? (MERGE_REFINE | MERGE_NO_COMBINE) : MERGE_NO_HIST;
@@ -235,6 +236,7 @@ struct Shape {
     int threads, l2;  // threads per block, log2 of the histogram replicas
     size_t lds;       // dynamic LDS per block
     int blocks, bpc;  // blocks of the launch (resident ones on every CU), blocks per CU
+    int fix_l2;       // the fixed histogram layout (= l2), or 0
 };
 
 void apply_shape(vegas_batch::Bucket& bk, const Shape& sh)
@@ -243,6 +245,7 @@ void apply_shape(vegas_batch::Bucket& bk, const Shape& sh)
     bk.hrep_log2 = sh.l2;
     bk.lds = sh.lds;
     bk.blocks = sh.blocks;
+    bk.fix_l2 = sh.fix_l2;
 }
 
 int env_int(const char* name)
@@ -458,12 +461,21 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
         return bail(fail(VEGAS_EINVAL, "VEGAS_BATCH_REPLICAS must be 1, 2, 4, 8 or 16"));
     std::vector<std::vector<Shape>> shapes;
     for (int dm : {64, 32, 16, 8, 4}) {
+        // the fixed histogram layout (8 or 16 replicas) when every problem of
+        // the bucket has at most kBatchFixBins bins
+        bool fixable = dm <= 16;
+        for (int p = 0; p < n; ++p)
+            if (dmax_of(descs[p].dim) == dm && descs[p].n_bins > kBatchFixBins) fixable = false;
+        auto fix_of = [&](int l2) { return fixable && (l2 == 3 || l2 == 4) ? l2 : 0; };
         auto lds_for = [&](int rep) {
+            const int fl2 = fix_of(rep == 16 ? 4 : rep == 8 ? 3 : 0);
             size_t m = 0;
             for (int p = 0; p < n; ++p)
                 if (dmax_of(descs[p].dim) == dm)
-                    m = std::max(m, lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, rep));
-            return m;
+                    m = std::max(m, fl2 ? lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, 0)
+                                        : lds_bytes(b->prec, b->kind, descs[p].dim, descs[p].n_bins, rep));
+            // fixed layout: the histogram [dm][kBatchFixBins][rep] first, then the table
+            return fl2 && m ? m + size_t(dm) * kBatchFixBins * rep * sizeof(double) : m;
         };
         if (lds_for(1) == 0) continue;  // no problem in this bucket
         std::vector<Shape> cand;
@@ -474,8 +486,8 @@ vegas_status vegas_batch_plan(vegas_batch** out, const vegas_desc* descs, const 
                 const size_t lds = lds_for(1 << l2);
                 // 256: the kernel's static LDS (work item, wave partials)
                 if (lds + 256 > kLdsLimit) continue;
-                const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th);
-                cand.push_back(Shape{th, l2, lds, std::max(1, cus * bpc), bpc});
+                const int bpc = batch_max_blocks_per_cu(b->prec, b->kind, dm, lds, th, fix_of(l2));
+                cand.push_back(Shape{th, l2, lds, std::max(1, cus * bpc), bpc, fix_of(l2)});
             }
         }
         if (cand.empty())

@@ -23,21 +23,33 @@ struct BatchMinWaves {
     static constexpr int value = 4;
 };
 
-template <class P, int KIND, int DMAX, bool HIST>
+// Fixed histogram layout (FRL2 = log2 of the replicas, 3 or 4; 0: general),
+// for buckets whose problems all have N <= kBatchFixBins: the histogram
+// starts the LDS with a compile-time stride of 64 bins x 2^FRL2 replicas per
+// dimension, so an atomic's address is one shift-add of the bin onto the
+// lane's replica offset, with the dimension's offset in the instruction's
+// immediate field; the problem's grid table follows it.
+template <class P, int KIND, int DMAX, bool HIST, int FRL2>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMinWaves<P, DMAX>::value, 8))) void k_batch_sample(
     BatchArgs a)
 {
+    constexpr bool FIX = HIST && FRL2 > 0;
+    static_assert(!FIX || DMAX <= 16, "fixed layout: d <= 16 only");
+    constexpr int kDimBytes = kBatchFixBins << (FRL2 + 3);
+    constexpr size_t kFixBytes = FIX ? size_t(DMAX) * kDimBytes : 0;
     using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(128) unsigned char smem[];
     __shared__ int s_item;
     __shared__ double red[kBlock / 64];
     // histogram [dim][bin][replica], lane l adding into replica l mod rep
-    const int rl2 = a.hrep_log2, rep = 1 << rl2;
+    const int rl2 = FIX ? FRL2 : a.hrep_log2, rep = 1 << rl2;
     const int lrep = int(threadIdx.x) & (rep - 1);
     int cur = -1;
     int d = 0, N = 0, dN = 0;
-    tab_t* tab = reinterpret_cast<tab_t*>(smem);
-    double* hist = nullptr;
+    tab_t* tab = reinterpret_cast<tab_t*>(smem + kFixBytes);
+    double* hist = FIX ? reinterpret_cast<double*>(smem) : nullptr;
+    // the lane's replica within the bin: byte offset lrep * 8 (fixed layout)
+    unsigned char* hlane = smem + (lrep << 3);
     EvalConsts<P, KIND, DMAX> cst;
     uint32_t key0 = 0, key1 = 0, ctr3 = 0;
     for (;;) {
@@ -59,10 +71,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
             for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
-            hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
+            if constexpr (!FIX) hist = reinterpret_cast<double*>(smem + ((size_t(dN) * sizeof(tab_t) + 127) & ~size_t(127)));
         }
-        if constexpr (HIST)
-            for (int k = threadIdx.x; k < (dN << rl2); k += blockDim.x) hist[k] = 0.0;
+        if constexpr (HIST) {
+            const int nh = (FIX ? d * kBatchFixBins : dN) << rl2;
+            for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0.0;
+        }
         __syncthreads();
 
         double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -85,7 +99,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
                 g1 = g2 = 0.0;
                 ng = 0;
             }
-            if constexpr (HIST) {
+            if constexpr (FIX) {
+#pragma unroll
+                for (int i = 0; i < DMAX; ++i)
+                    if (i < d)
+                        lds_atomic_add(reinterpret_cast<double*>(hlane + (i * kDimBytes + (ev.b[i] << (FRL2 + 3)))), v2);
+            } else if constexpr (HIST) {
 #pragma unroll
                 for (int i = 0; i < DMAX; ++i)
                     if (i < d) lds_atomic_add(&(hist + (i * N << rl2))[(ev.b[i] << rl2) | lrep], v2);
@@ -103,8 +122,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         }
         if constexpr (HIST) {
             for (int k = threadIdx.x; k < dN; k += blockDim.x) {
+                // bin (i, b) of the row at k = i N + b; fixed layout: 64 bins per dimension
+                const int hk = FIX ? k + (k / N) * (kBatchFixBins - N) : k;
                 double h = 0.0;
-                for (int r = 0; r < rep; ++r) h += hist[(k << rl2) + r];
+                for (int r = 0; r < rep; ++r) h += hist[(hk << rl2) + r];
                 row[2 + k] = h;
             }
         }
@@ -199,47 +220,62 @@ hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind,
 // ---------------------------------------------------------------------------
 
 template <class P, int KIND, bool HIST>
-static const void* batch_fn(int dmax)
+static const void* batch_fn(int dmax, int fix_l2)
 {
+    if constexpr (HIST) {
+        if (fix_l2 == 3 || fix_l2 == 4) {
+            const bool r16 = fix_l2 == 4;
+            switch (dmax) {
+            case 4: return r16 ? reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4, true, 4>)
+                               : reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4, true, 3>);
+            case 8: return r16 ? reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8, true, 4>)
+                               : reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8, true, 3>);
+            case 16: return r16 ? reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16, true, 4>)
+                                : reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16, true, 3>);
+            default: break;
+            }
+        }
+    }
     switch (dmax) {
-    case 4: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4, HIST>);
-    case 8: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8, HIST>);
-    case 16: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16, HIST>);
-    case 32: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 32, HIST>);
-    default: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 64, HIST>);
+    case 4: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 4, HIST, 0>);
+    case 8: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 8, HIST, 0>);
+    case 16: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 16, HIST, 0>);
+    case 32: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 32, HIST, 0>);
+    default: return reinterpret_cast<const void*>(&k_batch_sample<P, KIND, 64, HIST, 0>);
     }
 }
 
 template <class P, bool HIST>
-static const void* batch_fn_kind(int kind, int dmax)
+static const void* batch_fn_kind(int kind, int dmax, int fix_l2)
 {
     switch (kind) {
-    case GAUSS: return batch_fn<P, GAUSS, HIST>(dmax);
-    case BIMODAL: return batch_fn<P, BIMODAL, HIST>(dmax);
-    case GENZ_DISC: return batch_fn<P, GENZ_DISC, HIST>(dmax);
-    default: return batch_fn<P, GENZ_PEAK, HIST>(dmax);
+    case GAUSS: return batch_fn<P, GAUSS, HIST>(dmax, fix_l2);
+    case BIMODAL: return batch_fn<P, BIMODAL, HIST>(dmax, fix_l2);
+    case GENZ_DISC: return batch_fn<P, GENZ_DISC, HIST>(dmax, fix_l2);
+    default: return batch_fn<P, GENZ_PEAK, HIST>(dmax, fix_l2);
     }
 }
 
-static const void* batch_kernel(int prec, int kind, int dmax, bool hist)
+static const void* batch_kernel(int prec, int kind, int dmax, bool hist, int fix_l2)
 {
-    if (hist) return prec == FP64 ? batch_fn_kind<P64, true>(kind, dmax) : batch_fn_kind<P32, true>(kind, dmax);
-    return prec == FP64 ? batch_fn_kind<P64, false>(kind, dmax) : batch_fn_kind<P32, false>(kind, dmax);
+    if (hist)
+        return prec == FP64 ? batch_fn_kind<P64, true>(kind, dmax, fix_l2) : batch_fn_kind<P32, true>(kind, dmax, fix_l2);
+    return prec == FP64 ? batch_fn_kind<P64, false>(kind, dmax, 0) : batch_fn_kind<P32, false>(kind, dmax, 0);
 }
 
 // Without histograms the launch keeps the same grid (and LDS size): it is a
 // work queue, so residency only sets how many blocks share the items.
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               int threads, bool hist, hipStream_t s)
+                               int threads, bool hist, int fix_l2, hipStream_t s)
 {
     void* args[] = {const_cast<BatchArgs*>(&a)};
-    return hipLaunchKernel(batch_kernel(prec, kind, dmax, hist), dim3(blocks), dim3(threads), args, lds, s);
+    return hipLaunchKernel(batch_kernel(prec, kind, dmax, hist, fix_l2), dim3(blocks), dim3(threads), args, lds, s);
 }
 
-int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads)
+int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads, int fix_l2)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax, true), threads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(prec, kind, dmax, true, fix_l2), threads, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;

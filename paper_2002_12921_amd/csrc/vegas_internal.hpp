@@ -318,9 +318,13 @@ hipError_t launch_reset_results(double* records, int32_t* rec_flag, DevResult* r
 hipError_t launch_copy_last(const DevResult* result, double* out2, hipStream_t s);
 int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int rep);
 
+// Fixed histogram layout of the batch event kernel (buckets with d <= 16 whose
+// problems all have n_bins <= kBatchFixBins, 8 or 16 replicas): fix_l2 = log2
+// of the replicas, 0 for the general layout.
+constexpr int kBatchFixBins = 64;
 hipError_t launch_batch_sample(int prec, int kind, int dmax, size_t lds, const BatchArgs& a, int blocks,
-                               int threads, bool hist, hipStream_t s);
-int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads);
+                               int threads, bool hist, int fix_l2, hipStream_t s);
+int batch_max_blocks_per_cu(int prec, int kind, int dmax, size_t lds, int threads, int fix_l2);
 hipError_t launch_batch_finish(const BatchArgs& a, int dmax, int kind, int rec_idx, int flags, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, int dmax, int n_rec, int kind, hipStream_t s);
 hipError_t launch_batch_combine(const BatchArgs& a, int n_rec, hipStream_t s);
