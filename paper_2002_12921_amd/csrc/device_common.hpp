@@ -228,8 +228,10 @@ struct EventEval {
         bool inside = true;               // DISC: all x_i > a_i
         int ewl = 0;                      // FP32: exponent taken out of w
         const uint32_t elo = uint32_t(e), ehi = uint32_t(e >> 32);
+        // one Philox call per group of four dimensions (the last group may be
+        // partial: DMAX need not be a multiple of 4)
 #pragma unroll
-        for (int g = 0; g < DMAX / 4; ++g) {
+        for (int g = 0; g < (DMAX + 3) / 4; ++g) {
             if (4 * g < d) {
                 const U4 k = philox4x32_10(elo, ehi, t, ctr3 + uint32_t(g), key0, key1);
                 // the group's four bins and table entries first, so that its

@@ -23,12 +23,94 @@ struct BatchMinWaves {
     static constexpr int value = 4;
 };
 
+// The events of one work item into the block's LDS histogram and the item's
+// (S1, S2) row.  DE > 0: compiled for exactly DE dimensions (the problem's
+// d), with no per-dimension guards, so the whole event runs as one block of
+// straight-line code; DE = 0: each dimension is guarded against d <= DMAX.
+// hist/hlane: the general layout's histogram, or the fixed layout's lane
+// base (FRL2 > 0).
+template <class P, int KIND, int DMAX, int DE, bool HIST, int FRL2>
+__device__ __forceinline__ void batch_item_events(const BatchArgs& a, const BatchItem& it, const BatchProblem& pr,
+                                                  const typename TabEntry<P, KIND>::type* tab, double* hist,
+                                                  unsigned char* hlane, int rl2, int lrep, int d, int N, double* red)
+{
+    constexpr bool FIX = HIST && FRL2 > 0;
+    constexpr int kDimBytes = kBatchFixBins << (FRL2 + 3);
+    constexpr int DM = DE > 0 ? DE : DMAX;
+    EvalConsts<P, KIND, DM> cst;
+    cst.load(pr.cst, pr.thr, d);
+    const uint32_t key0 = pr.key0, key1 = pr.key1, ctr3 = pr.ctr3;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, g1 = 0.0, g2 = 0.0;
+    int ng = 0;
+    for (uint64_t k = threadIdx.x; k < it.n; k += blockDim.x) {
+        EventEval<P, KIND, DM, (DE > 0)> ev;
+        ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
+        double v, v2;
+        {
+            // rounded as written in every variant (with or without histograms)
+#pragma clang fp contract(off)
+            v = ev.value(cst);
+            v2 = v * v;
+            g1 += v;
+            g2 += v2;
+        }
+        if (++ng == kGroup) {
+            kahan_add(s1, c1, g1);
+            kahan_add(s2, c2, g2);
+            g1 = g2 = 0.0;
+            ng = 0;
+        }
+        if constexpr (FIX) {
+#pragma unroll
+            for (int i = 0; i < DM; ++i)
+                if (DE > 0 || i < d)
+                    lds_atomic_add(reinterpret_cast<double*>(hlane + (i * kDimBytes + (ev.b[i] << (FRL2 + 3)))), v2);
+        } else if constexpr (HIST) {
+#pragma unroll
+            for (int i = 0; i < DM; ++i)
+                if (DE > 0 || i < d) lds_atomic_add(&(hist + (i * N << rl2))[(ev.b[i] << rl2) | lrep], v2);
+        }
+    }
+    (void)lrep;
+    kahan_add(s1, c1, g1);
+    kahan_add(s2, c2, g2);
+    // block_sum synchronises, which also completes every histogram atomic
+    const double S1 = block_sum(s1 - c1, red);
+    const double S2 = block_sum(s2 - c2, red);
+    double* row = a.partials + it.row_off;
+    if (threadIdx.x == 0) {
+        row[0] = S1;
+        row[1] = S2;
+    }
+}
+
+// The exact-d variant for d in [LO, DE] (an if-chain from DE down), the
+// guarded one below LO.
+template <class P, int KIND, int DMAX, int DE, int LO, bool HIST, int FRL2>
+__device__ __forceinline__ void batch_item_dispatch(const BatchArgs& a, const BatchItem& it, const BatchProblem& pr,
+                                                    const typename TabEntry<P, KIND>::type* tab, double* hist,
+                                                    unsigned char* hlane, int rl2, int lrep, int d, int N, double* red)
+{
+    if constexpr (DE < LO) {
+        batch_item_events<P, KIND, DMAX, 0, HIST, FRL2>(a, it, pr, tab, hist, hlane, rl2, lrep, d, N, red);
+    } else {
+        if (d == DE)
+            batch_item_events<P, KIND, DMAX, DE, HIST, FRL2>(a, it, pr, tab, hist, hlane, rl2, lrep, d, N, red);
+        else
+            batch_item_dispatch<P, KIND, DMAX, DE - 1, LO, HIST, FRL2>(a, it, pr, tab, hist, hlane, rl2, lrep, d, N,
+                                                                       red);
+    }
+}
+
 // Fixed histogram layout (FRL2 = log2 of the replicas, 3 or 4; 0: general),
 // for buckets whose problems all have N <= kBatchFixBins: the histogram
 // starts the LDS with a compile-time stride of 64 bins x 2^FRL2 replicas per
 // dimension, so an atomic's address is one shift-add of the bin onto the
 // lane's replica offset, with the dimension's offset in the instruction's
 // immediate field; the problem's grid table follows it.
+// The Gaussian's buckets up to d = 16 run each item with the loop compiled
+// for the problem's exact d (items are sorted by d, so a block seldom
+// changes variant); other integrands and larger buckets guard each dimension.
 template <class P, int KIND, int DMAX, bool HIST, int FRL2>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMinWaves<P, DMAX>::value, 8))) void k_batch_sample(
     BatchArgs a)
@@ -37,6 +119,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
     static_assert(!FIX || DMAX <= 16, "fixed layout: d <= 16 only");
     constexpr int kDimBytes = kBatchFixBins << (FRL2 + 3);
     constexpr size_t kFixBytes = FIX ? size_t(DMAX) * kDimBytes : 0;
+    // the bucket's d range: (DMAX/2, DMAX], and 1..4 for the smallest
+    constexpr int kLo = DMAX <= 4 ? 1 : DMAX / 2 + 1;
+    constexpr bool kExact = KIND == GAUSS && DMAX <= 16;
     using tab_t = typename TabEntry<P, KIND>::type;
     extern __shared__ __align__(128) unsigned char smem[];
     __shared__ int s_item;
@@ -50,24 +135,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
     double* hist = FIX ? reinterpret_cast<double*>(smem) : nullptr;
     // the lane's replica within the bin: byte offset lrep * 8 (fixed layout)
     unsigned char* hlane = smem + (lrep << 3);
-    EvalConsts<P, KIND, DMAX> cst;
-    uint32_t key0 = 0, key1 = 0, ctr3 = 0;
     for (;;) {
         if (threadIdx.x == 0) s_item = a.item_lo + int(atomicAdd(a.queue, 1u));
         __syncthreads();
         const int item = s_item;
         if (item >= a.item_hi) break;  // every block leaves once the queue is empty
         const BatchItem it = a.items[item];
+        const BatchProblem& pr = a.probs[it.prob];
         if (it.prob != cur) {
             cur = it.prob;
-            const BatchProblem& pr = a.probs[cur];
             d = pr.d;
             N = pr.N;
             dN = d * N;
-            key0 = pr.key0;
-            key1 = pr.key1;
-            ctr3 = pr.ctr3;
-            cst.load(pr.cst, pr.thr, d);
             const tab_t* gtab = P::is64 ? reinterpret_cast<const tab_t*>(pr.tab64)
                                         : reinterpret_cast<const tab_t*>(pr.tab32);
             for (int k = threadIdx.x; k < dN; k += blockDim.x) tab[k] = gtab[k];
@@ -79,48 +158,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         }
         __syncthreads();
 
-        double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, g1 = 0.0, g2 = 0.0;
-        int ng = 0;
-        for (uint64_t k = threadIdx.x; k < it.n; k += blockDim.x) {
-            EventEval<P, KIND, DMAX> ev;
-            ev.run(cst, tab, it.e0 + k, a.t, ctr3, key0, key1, d, N);
-            double v, v2;
-            {
-                // rounded as written in every variant (with or without histograms)
-#pragma clang fp contract(off)
-                v = ev.value(cst);
-                v2 = v * v;
-                g1 += v;
-                g2 += v2;
-            }
-            if (++ng == kGroup) {
-                kahan_add(s1, c1, g1);
-                kahan_add(s2, c2, g2);
-                g1 = g2 = 0.0;
-                ng = 0;
-            }
-            if constexpr (FIX) {
-#pragma unroll
-                for (int i = 0; i < DMAX; ++i)
-                    if (i < d)
-                        lds_atomic_add(reinterpret_cast<double*>(hlane + (i * kDimBytes + (ev.b[i] << (FRL2 + 3)))), v2);
-            } else if constexpr (HIST) {
-#pragma unroll
-                for (int i = 0; i < DMAX; ++i)
-                    if (i < d) lds_atomic_add(&(hist + (i * N << rl2))[(ev.b[i] << rl2) | lrep], v2);
-            }
-        }
-        kahan_add(s1, c1, g1);
-        kahan_add(s2, c2, g2);
-        // block_sum synchronises, which also completes every histogram atomic
-        const double S1 = block_sum(s1 - c1, red);
-        const double S2 = block_sum(s2 - c2, red);
-        double* row = a.partials + it.row_off;
-        if (threadIdx.x == 0) {
-            row[0] = S1;
-            row[1] = S2;
-        }
+        if constexpr (kExact)
+            batch_item_dispatch<P, KIND, DMAX, DMAX, kLo, HIST, FRL2>(a, it, pr, tab, hist, hlane, rl2, lrep, d, N,
+                                                                     red);
+        else
+            batch_item_events<P, KIND, DMAX, 0, HIST, FRL2>(a, it, pr, tab, hist, hlane, rl2, lrep, d, N, red);
+
         if constexpr (HIST) {
+            double* row = a.partials + it.row_off;
             for (int k = threadIdx.x; k < dN; k += blockDim.x) {
                 // bin (i, b) of the row at k = i N + b; fixed layout: 64 bins per dimension
                 const int hk = FIX ? k + (k / N) * (kBatchFixBins - N) : k;
@@ -131,6 +176,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         }
         __syncthreads();
     }
+    (void)kDimBytes;
 }
 
 // Per problem and column group: reduce the problem's item rows, record the
