@@ -52,6 +52,35 @@ def test_batch_fp64_matches_oracle():
         assert np.max(np.abs(b.edges(p) - ref["edges"])) <= 1e-12, p
 
 
+@pytest.mark.parametrize("kind", ["genz_disc", "genz_peak", "bimodal"])
+def test_batch_other_integrands_fp64_match_oracle(kind):
+    """Batches of the other integrands (each dimension guarded against the
+    problem's d; the fixed histogram layout where N <= 64): d across the three
+    smallest buckets, FP64, every problem against its oracle run at 1e-12."""
+    kid = {"genz_disc": oracle.GENZ_DISC, "genz_peak": oracle.GENZ_PEAK, "bimodal": oracle.BIMODAL}[kind]
+    probs = []
+    for p, (d, N, n) in enumerate([(3, 20, 20_000), (7, 50, 30_000), (12, 20, 25_000), (16, 50, 40_000)]):
+        if kind == "bimodal":
+            params = [0.2] + [0.35] * d + [0.65] * d
+        else:
+            params = workloads.genz16(kind, d)
+        probs.append({"dim": d, "n_bins": N, "integrand": kind, "params": params, "n_events": n,
+                      "precision": "fp64", "problem": p})
+    n_iter, n_adapt = 4, 2
+    b = VegasBatch(probs, n_iter, n_adapt)
+    b.run()
+    res = b.results()
+    for p, q in enumerate(probs):
+        pr = oracle.Problem(q["dim"], q["n_bins"], kid, q["params"], seed=0, problem=q["problem"])
+        ref = oracle.run(pr, oracle.uniform_edges(q["dim"], q["n_bins"]), n_iter, q["n_events"],
+                         [1] * n_adapt + [0] * (n_iter - n_adapt), [0] * n_adapt + [1] * (n_iter - n_adapt))
+        I, s, c = ref["final"]
+        assert abs(res[p]["integral"] - I) <= 1e-12 * abs(I), (kind, p)
+        assert abs(res[p]["sigma"] - s) <= 1e-12 * s, (kind, p)
+        assert np.max(np.abs(b.edges(p) - ref["edges"])) <= 1e-12, (kind, p)
+    b.close()
+
+
 def test_batch_mixed_matches_single_problem_path():
     probs = _small_batch("fp32_mixed", n=6, seed=11)
     n_iter, n_adapt = 4, 2
