@@ -81,6 +81,26 @@ def test_batch_other_integrands_fp64_match_oracle(kind):
     b.close()
 
 
+def test_batch_wide_grids_general_layout():
+    """Grids of more than 64 bins (the batch kernel's general histogram
+    layout, with whatever replicas the tuner keeps) with the Gaussian's
+    exact-d loops: FP64, every problem against its oracle run at 1e-12."""
+    probs = [{"dim": d, "n_bins": N, "params": [0.2] + [0.5] * d, "n_events": n, "precision": "fp64",
+              "problem": p}
+             for p, (d, N, n) in enumerate([(2, 100, 20_000), (6, 80, 30_000), (11, 100, 25_000), (16, 80, 30_000)])]
+    n_iter, n_adapt = 4, 2
+    b = VegasBatch(probs, n_iter, n_adapt)
+    b.run()
+    res = b.results()
+    for p, q in enumerate(probs):
+        ref = _oracle_run(q, n_iter, n_adapt)
+        I, s, c = ref["final"]
+        assert abs(res[p]["integral"] - I) <= 1e-12 * abs(I), p
+        assert abs(res[p]["sigma"] - s) <= 1e-12 * s, p
+        assert np.max(np.abs(b.edges(p) - ref["edges"])) <= 1e-12, p
+    b.close()
+
+
 def test_batch_mixed_matches_single_problem_path():
     probs = _small_batch("fp32_mixed", n=6, seed=11)
     n_iter, n_adapt = 4, 2
