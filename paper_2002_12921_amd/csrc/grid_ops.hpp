@@ -308,7 +308,7 @@ __device__ static void refine_dim_wave(const MergeArgs& a, int i, double hb, dou
 
 // Stand-alone refinement of dimension i by the calling block from h (LDS):
 // one wave for N <= 64, the whole block otherwise.
-__device__ static void refine_any(const MergeArgs& a, int i, const double* h, const double* Eo)
+__device__ static inline void refine_any(const MergeArgs& a, int i, const double* h, const double* Eo)
 {
     if (a.N <= 64) {
         if (threadIdx.x < 64) {

@@ -176,7 +176,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BatchMin
         }
         __syncthreads();
     }
-    (void)kDimBytes;
 }
 
 // Per problem and column group: reduce the problem's item rows, record the
