@@ -923,6 +923,33 @@ def test_no_hist_iterations(prec):
     assert a.last_iteration()[0] == b.last_iteration()[0]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("d,N", [(20, 100), (6, 40), (5, 7)])
+def test_no_hist_bimodal_same_bits(prec, d, N):
+    """The bimodal integrand with and without histograms: the same S1 and S2
+    bits on a grid adapted to both centres (kernels of different LDS layouts
+    and register budgets), and both match the oracle, histograms included.
+    Partly adapted, the d = 20 grid leaves the sums to events between the
+    peaks, where each term's offset from its farther centre decides the
+    value: the FP32 path meets the tolerance there only with each offset
+    rounded once from FP64 at its own size."""
+    params = [0.05] + [1 / 3] * d + [2 / 3] * d
+    M = 300_001
+    E = _adapted_edges(d, N, params, kind=oracle.BIMODAL, iters=3, n=20_000)
+    a = Vegas(d, N, "bimodal", params, prec, seed=5)
+    b = Vegas(d, N, "bimodal", params, prec, seed=5)
+    for v in (a, b):
+        v.set_edges(E)
+    a.iterate(M)
+    b.iterate(M, hist=False)
+    Sa, Sb = a.last_iteration(), b.last_iteration()
+    assert Sa[0] == Sb[0] and Sa[1] == Sb[1]
+    o1, o2, Ho = oracle.accumulate(oracle.Problem(d, N, oracle.BIMODAL, params, seed=5), E, 0, M)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(Sa[0] - o1) <= tol * abs(o1) and abs(Sa[1] - o2) <= tol * abs(o2)
+    assert _hist_close(Sa[2], Ho, tol)
+
+
 def test_time_event_kernel_leaves_state():
     """The measurement entry point runs the event kernel only: the iteration
     index, the records and the grid do not move."""
