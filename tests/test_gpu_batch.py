@@ -81,6 +81,43 @@ def test_batch_other_integrands_fp64_match_oracle(kind):
     b.close()
 
 
+@pytest.mark.parametrize("kind", ["genz_disc", "genz_peak", "bimodal"])
+def test_batch_other_integrands_mixed_lockstep(kind):
+    """FP32-mixed batches of the other integrands, stepped one iteration at a
+    time: every problem's S1, S2 and (adaptation iterations) every histogram
+    bin against the oracle on the batch's own grid at 1e-6, and every
+    refinement against the oracle's refinement of the batch's histograms at
+    1e-12; d across the three smallest buckets, even and odd N."""
+    kid = {"genz_disc": oracle.GENZ_DISC, "genz_peak": oracle.GENZ_PEAK, "bimodal": oracle.BIMODAL}[kind]
+    probs = []
+    for p, (d, N, n) in enumerate([(3, 21, 20_000), (7, 50, 30_000), (12, 20, 25_000), (16, 50, 40_000)]):
+        if kind == "bimodal":
+            params = [0.2] + [0.35] * d + [0.65] * d
+        else:
+            params = workloads.genz16(kind, d)
+        probs.append({"dim": d, "n_bins": N, "integrand": kind, "params": params, "n_events": n,
+                      "precision": "fp32_mixed", "problem": p})
+    n_iter, n_adapt = 4, 2
+    b = VegasBatch(probs, n_iter, n_adapt)
+    tol = 1e-6
+    for k in range(n_iter):
+        before = [b.edges(p) for p in range(len(probs))]
+        b.step(k)
+        for p, q in enumerate(probs):
+            pr = oracle.Problem(q["dim"], q["n_bins"], kid, q["params"], seed=0, problem=q["problem"])
+            S1, S2, H = b.last_iteration(p)
+            o1, o2, Ho = oracle.accumulate(pr, before[p], k, q["n_events"])
+            assert abs(S1 - o1) <= tol * abs(o1), (kind, p, k, S1, o1)
+            assert abs(S2 - o2) <= tol * abs(o2), (kind, p, k, S2, o2)
+            E = b.edges(p)
+            if k < n_adapt:
+                assert _hist_close(H, Ho, tol), (kind, p, k)
+                assert np.max(np.abs(E - oracle.refine(H, before[p], 1.5))) <= 1e-12, (kind, p, k)
+            else:
+                assert np.array_equal(E, before[p])
+    b.close()
+
+
 def test_batch_wide_grids_general_layout():
     """Grids of more than 64 bins (the batch kernel's general histogram
     layout, with whatever replicas the tuner keeps) with the Gaussian's
