@@ -395,7 +395,7 @@ static int dim_bucket(int d)
     }
 
 // The histogram mode of a launch: none, or the fixed layout where it applies
-// (d in {4, 8}, N <= 64, 16 replicas), or the general one.
+// (d in {4, 8, 12, 16}, N <= 64, 16 replicas), or the general one.
 static int hist_mode(int d, int N, int rep, bool hist)
 {
     if (!hist) return kHistNone;

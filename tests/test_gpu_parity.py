@@ -244,11 +244,11 @@ def _hist_close(Hg, Ho, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
-@pytest.mark.parametrize("d,N", [(4, 64), (8, 13), (8, 50), (8, 65), (5, 50), (3, 7)])
+@pytest.mark.parametrize("d,N", [(4, 64), (8, 13), (8, 50), (8, 65), (5, 50), (3, 7), (12, 50), (16, 33)])
 def test_histogram_layouts(prec, tol, d, N):
     """Sums and histograms with 16 replicas per bin (the fixed-stride layout
-    where d is 4 or 8 and N <= 64), with one copy, and with the automatic
-    choice, each against the oracle on the same adapted grid."""
+    where d is 4, 8, 12 or 16 and N <= 64), with one copy, and with the
+    automatic choice, each against the oracle on the same adapted grid."""
     params = _gauss(d, mu=0.37)
     E = _adapted_edges(d, N, params)
     M = 300_007
