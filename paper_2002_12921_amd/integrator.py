@@ -160,6 +160,11 @@ class Vegas:
         (FP64, d + 1) and (I_t, sigma_t) into out (FP64, 2): one library call.
         rest: None (all parameters in params), or the parameters after the
         first, with params holding only the first (a, then mu), same dtype."""
+        assert params.is_cuda and params.is_contiguous() and params.dtype in (torch.float32, torch.float64)
+        assert rest is None or (rest.is_cuda and rest.is_contiguous() and rest.dtype == params.dtype
+                                and params.numel() == 1)
+        assert G.is_cuda and G.dtype == torch.float64 and G.is_contiguous() and G.numel() >= self.dim + 1
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 2
         n = params.numel() if rest is None else 1 + rest.numel()
         check(lib().vegas_forward_grad(self._ctx, params.data_ptr(), None if rest is None else rest.data_ptr(), n,
                                        1 if params.dtype == torch.float32 else 0, int(n_events),
@@ -209,8 +214,10 @@ class Vegas:
 
     def grad_scale(self, G: torch.Tensor, gout: torch.Tensor, grad: torch.Tensor):
         """grad = gout * G (d + 1 values), one rounding to grad's dtype."""
-        assert G.is_cuda and G.dtype == torch.float64 and gout.is_cuda and gout.dtype == torch.float64
+        assert G.is_cuda and G.dtype == torch.float64 and G.is_contiguous() and G.numel() >= self.dim + 1
+        assert gout.is_cuda and gout.dtype == torch.float64
         assert grad.is_cuda and grad.dtype in (torch.float64, torch.float32) and grad.is_contiguous()
+        assert grad.numel() >= self.dim + 1
         check(lib().vegas_grad_scale(G.data_ptr(), gout.data_ptr(), grad.data_ptr(), self.dim + 1,
                                      1 if grad.dtype == torch.float32 else 0, self._s()), "grad_scale")
 
