@@ -105,6 +105,8 @@ __device__ __forceinline__ float exp2_unit(float z) { return __builtin_amdgcn_ex
 struct BinConsts {
     uint32_t mul, add;  // N, floor(N/2)
     double h64;         // h / 2^32
+    double s32;         // 2^-32, read from memory: in a scalar register the FP64
+                        // fma delta = lo 2^-32 + h64 needs no copy of its addend
 };
 
 __device__ __forceinline__ void bin_words(uint32_t k, const BinConsts& bc, int& b, uint32_t& lo)
@@ -168,6 +170,7 @@ struct EvalConsts {
         bc.mul = N;
         bc.add = N >> 1;
         bc.h64 = (N & 1u) ? 0x1p-33 : 0.0;
+        bc.s32 = c->two_m32;
         C = c->C;
         Cf = c->Cf;
         Cw = c->Cw;
@@ -258,7 +261,7 @@ struct EventEval {
                         real ui, ubi = real(0), width;
                         real dl;
                         if constexpr (P::is64) {
-                            dl = fma(double(lo), 0x1p-32, c.bc.h64);
+                            dl = fma(double(lo), c.bc.s32, c.bc.h64);
                             width = tb.y;
                             ui = fma(dl, tb.y, tb.x);
                             if constexpr (KIND == BIMODAL) ubi = ui - c.p2[i];  // p2 = muB - muA

@@ -53,7 +53,7 @@ __device__ static void prepare_consts(int prec, int kind, int d, int N, const do
     const double log2e = 1.4426950408889634074;
     c->n_bins = N;
     c->pad1 = 0;
-    c->pad2 = 0.0;
+    c->two_m32 = 0x1p-32;
     c->dscale32 = width_scale32(N);
     const int ws = int(rint(log2(double(N))));
     double nd = 1.0;

@@ -31,12 +31,13 @@ namespace user {
 constexpr int D = VEGAS_DIM;
 static_assert(D >= 1 && D <= kMaxDim, "VEGAS_DIM out of range");
 
-__device__ __forceinline__ BinConsts bin_consts(int N)
+__device__ __forceinline__ BinConsts bin_consts(int N, const DevConst* c)
 {
     BinConsts bc;
     bc.mul = uint32_t(N);
     bc.add = uint32_t(N) >> 1;
     bc.h64 = (N & 1) ? 0x1p-33 : 0.0;
+    bc.s32 = c->two_m32;
     return bc;
 }
 
@@ -124,7 +125,7 @@ struct Event {
                     uint32_t lo;
                     bin_words(k.w[q], bc, bi, lo);
                     const tab_t tb = (tab + i * N)[bi];
-                    const double dl = fma(double(lo), 0x1p-32, bc.h64);
+                    const double dl = fma(double(lo), bc.s32, bc.h64);
                     b[i] = bi;
                     del[i] = dl;
                     x[i] = fma(dl, tb.y, tb.x);
@@ -169,7 +170,7 @@ __device__ __forceinline__ void sample(const SampleArgs& a, const double* __rest
         for (int k = threadIdx.x; k < dN * rep; k += blockDim.x) hist[k] = 0.0;
     __syncthreads();
 
-    const BinConsts bc = bin_consts(N);
+    const BinConsts bc = bin_consts(N, a.cst);
     const double C = a.cst->C;  // N^d (FP32: times 2^(-ws d))
     const float ds = map_scale(a.cst);
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
@@ -249,7 +250,7 @@ extern "C" __global__ __launch_bounds__(256) void vegas_user_dump(vegas::DumpArg
     const tab_t* gtab = static_cast<const tab_t*>(a.tab);
     for (int k = threadIdx.x; k < D * N; k += blockDim.x) tab[k] = gtab[k];
     __syncthreads();
-    const BinConsts bc = user::bin_consts(N);
+    const BinConsts bc = user::bin_consts(N, a.cst);
     const double Cw = a.cst->Cw;
     const float ds = user::map_scale(a.cst);
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;

@@ -49,7 +49,7 @@ struct DevConst {
     double inv_a;    // GAUSS, BIMODAL: 1/a (adjoint)
     int32_t n_bins;  // N (binning)
     int32_t pad1;
-    double pad2;
+    double two_m32;  // 2^-32
     float kexp32;    // (unused by the kernels; kept for the layout)
     float dscale32;  // 2^-ws
     float ka32;      // GAUSS: RN32(1/a^2) (adjoint)
