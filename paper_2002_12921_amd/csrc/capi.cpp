@@ -390,6 +390,7 @@ vegas_status init_ctx(vegas_ctx** out, const vegas_desc* desc, const char* sourc
             int bpc = 1;
             if (!source) {
                 bpc = sample_max_blocks_per_cu(c->prec, c->kind, c->d, c->N, th, 1 << l2);
+                if (bpc < 1) continue;  // beyond the kernel's largest block
             } else if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, c->usample[0], th, lds) != hipSuccess ||
                        bpc < 1) {
                 bpc = 1;

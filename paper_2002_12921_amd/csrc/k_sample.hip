@@ -39,9 +39,21 @@ constexpr int kFixDimBytes = kFixBins << (kFixRepLog2 + 3);
 // it still spilled 8 and took 70.0-70.8 us, at 6: 57.9-58.5 us.  4 elsewhere:
 // the discontinuous integrand and larger d would spill heavily, and the
 // FP32-mixed kernels reach 8 waves by themselves.
-template <class P, int KIND, int DMAX>
+// The FP64 discontinuous integrand with histograms at d = 16: its 16 FP64
+// c_i and thresholds leave too few scalar registers, and at 128 VGPRs (4
+// waves) it spilled 18 of them (72 bytes per lane, 37.6 MB of scratch traffic
+// per 1e7 events); it runs one 768-thread block per CU, 3 waves per SIMD,
+// without spills: 132.1-132.3 -> 123.4-123.6 us per 1e7 events.  (At d = 13,
+// in the guarded d <= 16 kernel, 3 waves ran slower: 167.0-167.6 -> 178.4-178.6.)
+template <class P, int KIND, int DMAX, bool EXACT, int HM>
+struct ThreeWaves {
+    static constexpr bool value = P::is64 && KIND == GENZ_DISC && DMAX == 16 && EXACT && HM != 0;
+};
+
+template <class P, int KIND, int DMAX, bool EXACT = false, int HM = 0>
 struct MinWaves {
-    static constexpr int value = (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 6 : 4;
+    static constexpr int value =
+        ThreeWaves<P, KIND, DMAX, EXACT, HM>::value ? 3 : (P::is64 && KIND != GENZ_DISC && DMAX <= 8) ? 6 : 4;
 };
 
 // Most waves per SIMD the kernel is compiled for.  Beyond d = 8 the kernels
@@ -50,14 +62,20 @@ struct MinWaves {
 // compiler cannot know from the dynamic LDS size: told so, it may use up to
 // 128 registers and keep an event's table reads in flight together instead
 // of waiting on each (the d = 20 bimodal kernel waited on every one).
-template <int DMAX, int HM>
+template <class P, int KIND, int DMAX, bool EXACT, int HM>
 struct MaxWaves {
-    static constexpr int value = (DMAX > 8 && HM != 0) ? 4 : 8;
+    static constexpr int value = ThreeWaves<P, KIND, DMAX, EXACT, HM>::value ? 3 : (DMAX > 8 && HM != 0) ? 4 : 8;
 };
 
 template <class P, int KIND, int DMAX, bool EXACT, int HM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWaves<P, KIND, DMAX>::value,
-                                                                         MaxWaves<DMAX, HM>::value))) void k_sample(
+struct MaxThreads {
+    static constexpr int value = ThreeWaves<P, KIND, DMAX, EXACT, HM>::value ? 768 : kBlock;
+};
+
+template <class P, int KIND, int DMAX, bool EXACT, int HM>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, MaxThreads<P, KIND, DMAX, EXACT, HM>::value),
+                          amdgpu_waves_per_eu(MinWaves<P, KIND, DMAX, EXACT, HM>::value,
+                                              MaxWaves<P, KIND, DMAX, EXACT, HM>::value))) void k_sample(
     SampleArgs a)
 {
     constexpr bool FIX = HM == kHistFixed;
@@ -533,6 +551,8 @@ int sample_max_blocks_per_cu(int prec, int kind, int d, int N, int threads, int 
 {
     int n = 0;
     const void* fn = sample_kernel(prec, kind, d, N, rep, true);
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) == hipSuccess && threads > at.maxThreadsPerBlock) return 0;  // not launchable
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, sample_lds(prec, kind, d, N, rep, true)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
