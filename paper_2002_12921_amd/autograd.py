@@ -33,6 +33,8 @@ class VegasIntegral(torch.autograd.Function):
         d = vegas.dim
         if mu.numel() != d or a.numel() != 1:
             raise ValueError(f"mu must have {d} elements and a one")
+        if not (mu.is_cuda and a.is_cuda):
+            raise ValueError("mu and a must be GPU tensors")
         # parameter layout of the Gaussian integrand: a, mu[0..d-1]; FP32
         # parameters go to the library as they are (it widens them, exactly)
         pt = torch.float32 if mu.dtype == torch.float32 and a.dtype == torch.float32 else torch.float64
@@ -45,10 +47,10 @@ class VegasIntegral(torch.autograd.Function):
             buf = torch.empty(d + 3, dtype=torch.float64, device=mu.device)
             G, out = buf[:d + 1], buf[d + 1:]
             if a.dtype == pt and mu.dtype == pt and mu.is_contiguous():
-                vegas.forward_grad(a.detach(), n_events, G, out, rest=mu.detach())
+                vegas._forward_grad(a.detach(), n_events, G, out, mu.detach())
             else:
                 params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
-                vegas.forward_grad(params, n_events, G, out)
+                vegas._forward_grad(params, n_events, G, out)
             ctx.G = G
         else:
             params = torch.cat([a.detach().reshape(1).to(pt), mu.detach().reshape(-1).to(pt)])
@@ -77,7 +79,7 @@ class VegasIntegral(torch.autograd.Function):
         # the library writes the parameters' dtype itself (one rounding)
         grad = torch.empty(d + 1, dtype=mu_dtype if same else torch.float64, device=g.device)
         if ctx.G is not None:
-            v.grad_scale(ctx.G, g, grad)
+            v._grad_scale(ctx.G, g, grad)
         else:
             grid_v, params_v = v.versions()
             if grid_v != ctx.versions[0]:

@@ -165,6 +165,12 @@ class Vegas:
                                 and params.numel() == 1)
         assert G.is_cuda and G.dtype == torch.float64 and G.is_contiguous() and G.numel() >= self.dim + 1
         assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 2
+        self._forward_grad(params, n_events, G, out, rest)
+
+    def _forward_grad(self, params, n_events, G, out, rest=None):
+        """forward_grad without the argument checks (for callers that built
+        the tensors themselves: the autograd function, whose step is
+        host-paced)."""
         n = params.numel() if rest is None else 1 + rest.numel()
         check(lib().vegas_forward_grad(self._ctx, params.data_ptr(), None if rest is None else rest.data_ptr(), n,
                                        1 if params.dtype == torch.float32 else 0, int(n_events),
@@ -218,6 +224,10 @@ class Vegas:
         assert gout.is_cuda and gout.dtype == torch.float64
         assert grad.is_cuda and grad.dtype in (torch.float64, torch.float32) and grad.is_contiguous()
         assert grad.numel() >= self.dim + 1
+        self._grad_scale(G, gout, grad)
+
+    def _grad_scale(self, G, gout, grad):
+        """grad_scale without the argument checks (see _forward_grad)."""
         check(lib().vegas_grad_scale(G.data_ptr(), gout.data_ptr(), grad.data_ptr(), self.dim + 1,
                                      1 if grad.dtype == torch.float32 else 0, self._s()), "grad_scale")
 

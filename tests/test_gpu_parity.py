@@ -682,6 +682,27 @@ def test_autograd_backward_after_refine(fused):
 
 
 @pytest.mark.parametrize("fused", [True, False])
+def test_autograd_rejects_bad_arguments(fused):
+    """Host tensors, wrong sizes and other integrands are refused before any
+    library call."""
+    from paper_2002_12921_amd.autograd import vegas_integral
+    d = 3
+    v = Vegas(d, 20, "gauss", [0.1] + [0.5] * d, "fp64")
+    mu = torch.full((d,), 0.5, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(0.1, dtype=torch.float64, requires_grad=True)
+    with pytest.raises(ValueError, match="GPU"):
+        vegas_integral(mu, a, v, 1000, fused)
+    with pytest.raises(ValueError, match="GPU"):
+        vegas_integral(mu.detach().cuda().requires_grad_(), a, v, 1000, fused)
+    with pytest.raises(ValueError, match="elements"):
+        vegas_integral(torch.full((d + 1,), 0.5, dtype=torch.float64, device="cuda"), a.cuda(), v, 1000, fused)
+    b = Vegas(d, 20, "bimodal", [0.1] + [0.3] * d + [0.6] * d, "fp64")
+    with pytest.raises(ValueError, match="Gaussian"):
+        vegas_integral(mu.detach().cuda(), a.detach().cuda(), b, 1000, fused)
+    assert v.iteration_index == 0 and b.iteration_index == 0
+
+
+@pytest.mark.parametrize("fused", [True, False])
 def test_autograd_many_forward_passes(fused):
     """More forward passes than a context has record slots (1024): none of
     them takes a slot, and a backward after them still matches the oracle."""
