@@ -865,6 +865,33 @@ def test_genz_d16_lockstep(kind, prec, tol):
         assert np.max(np.abs(v.edges() - oracle.refine(H, E, 1.5))) <= 1e-12
 
 
+@pytest.mark.parametrize("N", [50, 90])
+def test_genz_disc_fp64_d16_every_replica_count(N):
+    """The FP64 discontinuous kernels at d = 16 take at most 768 threads per
+    block: the automatic launch picks 768, and every replica count (fixed and
+    general layouts) and the kernel without histograms run at that size and
+    match the oracle."""
+    from paper_2002_12921_amd import workloads
+    d, M = 16, 200_003
+    params = workloads.genz16("genz_disc")
+    pr = oracle.Problem(d, N, oracle.GENZ_DISC, params, seed=3)
+    E = _adapted_edges(d, N, params, kind=oracle.GENZ_DISC, iters=2, n=20_000)
+    o1, o2, Ho = oracle.accumulate(pr, E, 0, M)
+    for rep in ((0, 16, 4, 1) if N <= 64 else (0, 8, 2, 1)):  # 16 copies of 90 bins exceed the LDS
+        v = Vegas(d, N, "genz_disc", params, "fp64", seed=3)
+        assert v.launch_info()["threads"] == 768
+        v.set_edges(E)
+        v.set_hist_replicas(rep)
+        v.iterate(M, combine=False)
+        S1, S2, H = v.last_iteration()
+        assert abs(S1 - o1) <= 1e-12 * abs(o1) and abs(S2 - o2) <= 1e-12 * abs(o2), rep
+        assert _hist_close(H, Ho, 1e-12), rep
+    w = Vegas(d, N, "genz_disc", params, "fp64", seed=3)
+    w.set_edges(E)
+    w.iterate(M, hist=False)
+    assert w.last_iteration()[0] == S1
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("kind", ["genz_disc", "genz_peak"])
 def test_full_size_genz_d16(kind, prec):
