@@ -7,14 +7,18 @@ path: points -> map -> integrand -> sums and histograms -> merge ->
 statistics -> refinement, all on the device.  The headline value is events/s
 of the FP32-mixed path; the FP64 path is timed the same way beside it.
 
-Also reported: the event kernel's roofline (VALU issue bound), the whole
-5 adaptation + 5 accumulation schedule for both precisions, plain Monte
-Carlo iterations (uniform grid, no histograms, no refinement), the same
-Gaussian as a user integrand compiled at run time (both precisions), the Genz
-discontinuous and product-peak integrands at d = 16, and the CPU
+Also reported: the event kernel's roofline (VALU issue bound, with the HBM
+traffic of its counter summary), the whole 5 adaptation + 5 accumulation
+schedule for both precisions (eager and as a HIP graph), accumulation and
+plain Monte Carlo iterations, the d = 4 FP64 case, the d = 20 bimodal
+integrand streamed in 1e7-event chunks, the 256-problem batch, the
+differentiable forward + backward, the same Gaussian as a user integrand
+compiled at run time (both precisions), the Genz discontinuous and
+product-peak integrands at d = 16, the VALU issue-rate probe, and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --profile-legs | --issue-probe
 """
 from __future__ import annotations
 
